@@ -1,0 +1,389 @@
+"""Pins for the CPU oracle: checks against facts fixed outside the oracle itself
+(an independent Philox implementation, library sin/cos, closed forms, exact
+invariants, brute force over a dense coupling matrix, exact conditional laws).
+
+The paper prints no worked example, energy or observable, so no printed value
+can serve as a pin; every function of the oracle is pinned by one of the checks
+below instead.
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+from tests import inputs
+
+F32, F64 = np.float32, np.float64
+ROCRAND_HDR = "/opt/rocm/include/rocrand/rocrand_philox4x32_10.h"
+
+
+# --------------------------------------------------------------------- Philox
+@pytest.fixture(scope="module")
+def rocrand_ref(tmp_path_factory):
+    if not os.path.exists(ROCRAND_HDR) or shutil.which("g++") is None:
+        pytest.skip("rocRAND header or g++ not available")
+    exe = tmp_path_factory.mktemp("philox") / "philox_ref"
+    src = os.path.join(os.path.dirname(__file__), "philox_rocrand_ref.cpp")
+    subprocess.run(["g++", "-O1", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include", src, "-o",
+                    str(exe)], check=True)
+    return str(exe)
+
+
+def test_philox_matches_rocrand(rocrand_ref):
+    rng = np.random.default_rng(7)
+    n = 2000
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64)
+    ctr[:, 1] %= 2 ** 30  # the reference positions its engine with 4*(c0 | c1<<32)
+    keys = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64)
+    edge = np.array([[0, 0, 0, 0, 0, 0], [2 ** 32 - 1, 2 ** 30 - 1, 2 ** 32 - 1, 2 ** 32 - 1,
+                                          2 ** 32 - 1, 2 ** 32 - 1], [1, 0, 0, 0, 1, 0]],
+                    dtype=np.uint64)
+    rows = np.concatenate([np.concatenate([ctr, keys], axis=1), edge])
+    text = "\n".join(" ".join(str(int(v)) for v in r) for r in rows) + "\n"
+    out = subprocess.run([rocrand_ref], input=text, capture_output=True, text=True, check=True)
+    ref = np.array([[int(v) for v in line.split()] for line in out.stdout.strip().splitlines()],
+                   dtype=np.uint64)
+    got = np.stack([O.philox(r[:4], int(r[4]) | (int(r[5]) << 32))[0] for r in rows])
+    np.testing.assert_array_equal(got.astype(np.uint64), ref)
+
+
+def test_philox_bits_balanced():
+    ctr = np.zeros((1 << 16, 4), dtype=np.uint32)
+    ctr[:, 0] = np.arange(1 << 16)
+    w = O.philox(ctr, 12345).ravel()
+    bits = np.unpackbits(w.view(np.uint8)).reshape(-1, 32).mean(axis=0)
+    # each bit is Bernoulli(1/2) over 2^18 words: sd 0.001
+    assert np.all(np.abs(bits - 0.5) < 0.006)
+
+
+# -------------------------------------------------------------------- uniforms
+def test_u01_exact_symmetric_and_open():
+    w = np.array([0, 1, 511, 512, 2 ** 31, 2 ** 32 - 1, 123456789], dtype=np.uint32)
+    u = O.u01(w)
+    assert u.min() > 0 and u.max() < 1
+    np.testing.assert_array_equal(u.astype(F32).astype(F64), u)  # exact in binary32
+    assert O.u01(np.array([0], np.uint32))[0] == 2.0 ** -24
+    assert O.u01(np.array([2 ** 32 - 1], np.uint32))[0] == 1 - 2.0 ** -24
+    rng = np.random.default_rng(3)
+    ww = rng.integers(0, 2 ** 32, size=10000, dtype=np.uint64).astype(np.uint32)
+    np.testing.assert_array_equal(O.u01(ww) + O.u01(~ww), np.ones(ww.size))
+
+
+# ------------------------------------------------------------------- sin / cos
+@pytest.mark.parametrize("dtype,tol", [(F32, 1.2e-7), (F64, 3.4e-16)])
+def test_sincos_against_libm(dtype, tol):
+    rng = np.random.default_rng(11)
+    w = rng.integers(0, 2 ** 32, size=4000, dtype=np.uint64).astype(np.uint32)
+    u = np.concatenate([O.u01(w), [2.0 ** -24, 0.125 + 2.0 ** -24, 0.25 - 2.0 ** -24, 0.5 + 2 ** -24,
+                                   0.75 - 2.0 ** -24, 1 - 2.0 ** -24]])
+    # reference in x87 extended precision (64-bit significand), so its own error is
+    # far below the bound being checked
+    two_pi = 2 * np.longdouble("3.14159265358979323846264338327950288")
+    err = 0.0
+    for x in u:
+        s, c = O.sincos_2pi(x, dtype)
+        arg = two_pi * np.longdouble(x)
+        err = max(err, abs(np.longdouble(s) - np.sin(arg)), abs(np.longdouble(c) - np.cos(arg)))
+    assert err < tol, err
+
+
+def test_poly_coefs_are_taylor_terms():
+    from fractions import Fraction
+    from math import factorial
+    # pi to 60 digits as an exact rational
+    pi = Fraction("3.141592653589793238462643383279502884197169399375105820974944")
+    c = O.poly_coefs(F64)
+    for k in range(18):
+        exact = (pi / 2) ** k / factorial(k) * (1 if (k // 2) % 2 == 0 else -1)
+        assert c[k] == float(exact), k  # float(Fraction) rounds correctly
+
+
+# ------------------------------------------------------------ initial state
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_init_spins_uniform_on_sphere(dtype):
+    s, J = O.init(24, 5, dtype)
+    n = np.linalg.norm(s.astype(F64), axis=0)
+    assert np.abs(n - 1).max() < (4e-7 if dtype == F32 else 1e-15)
+    for a in range(3):  # Archimedes: each component is U[-1, 1]
+        assert stats.kstest(s[a], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+    phi = np.arctan2(s[1], s[0])
+    assert stats.kstest(phi, stats.uniform(loc=-np.pi, scale=2 * np.pi).cdf).pvalue > 1e-3
+    cov = (s.astype(F64) @ s.astype(F64).T) / s.shape[1]
+    np.testing.assert_allclose(cov, np.eye(3) / 3, atol=0.01)
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_init_couplings_standard_normal(dtype):
+    _, J = O.init(24, 9, dtype)
+    for d in range(3):
+        assert stats.kstest(J[d], stats.norm.cdf).pvalue > 1e-3
+    assert abs(np.corrcoef(J[0], J[1])[0, 1]) < 0.03
+
+
+# ------------------------------------------------ energy and field: brute force
+def coupling_matrix(L: int, J: np.ndarray) -> np.ndarray:
+    """Dense symmetric matrix A with A[i, j] = sum of couplings on bonds joining i, j,
+    built by enumerating coordinates and the periodic distance between sites."""
+    N = L ** 3
+    A = np.zeros((N, N))
+    coords = [(i % L, (i // L) % L, i // (L * L)) for i in range(N)]
+    index = {c: i for i, c in enumerate(coords)}
+    for i, (x, y, z) in enumerate(coords):
+        for d, step in enumerate([(1, 0, 0), (0, 1, 0), (0, 0, 1)]):
+            j = index[((x + step[0]) % L, (y + step[1]) % L, (z + step[2]) % L)]
+            A[i, j] += J[d, i]
+            A[j, i] += J[d, i]
+    return A
+
+
+@pytest.mark.parametrize("L", [2, 4, 6])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_energy_and_field_brute_force(L, dtype):
+    s, J = inputs.random_state(L, 100 + L, dtype)
+    A = coupling_matrix(L, J.astype(F64))
+    S = s.astype(F64)
+    H = -0.5 * np.einsum("ai,ij,aj->", S, A, S)  # each bond once, eq. (1)
+    assert abs(O.energy(L, s, J) - H) <= 1e-12 * max(1.0, abs(H))
+    Hfield = A @ S.T  # local field, eq. (2)
+    tol = 2e-6 if dtype == F32 else 1e-14
+    for i in range(L ** 3):
+        x, y, z = i % L, (i // L) % L, i // (L * L)
+        h = O.local_field(L, s, J, x, y, z)
+        np.testing.assert_allclose(h, Hfield[i], atol=tol * 6)
+
+
+def test_energy_random_state_moments():
+    # sigma uniform and J ~ N(0,1) independent: E[H] = 0 and Var[H] = 3N * E[J^2] *
+    # E[(s.s')^2] = 3N * 1 * 1/3 = N.
+    L = 8
+    Hs = []
+    for seed in range(200):
+        s, J = inputs.random_state(L, seed, F64)
+        Hs.append(O.energy(L, s, J))
+    Hs = np.array(Hs) / np.sqrt(L ** 3)
+    assert abs(Hs.mean()) < 4 / np.sqrt(len(Hs))
+    assert 0.75 < Hs.var() < 1.3
+
+
+# ------------------------------------------------------------ over-relaxation
+@pytest.mark.parametrize("dtype,tol", [(F32, 3e-6), (F64, 1e-14)])
+def test_overrelax_invariants(dtype, tol):
+    rng = np.random.default_rng(2)
+    for _ in range(300):
+        h = rng.standard_normal(3).astype(dtype) * 3
+        s = rng.standard_normal(3)
+        s = (s / np.linalg.norm(s)).astype(dtype)
+        s1 = O.overrelax_site(h, s)
+        s2 = O.overrelax_site(h, s1)
+        hd, sd, s1d = h.astype(F64), s.astype(F64), s1.astype(F64)
+        assert abs(s1d @ hd - sd @ hd) <= tol * np.linalg.norm(hd) * 3
+        assert abs(np.linalg.norm(s1d) - np.linalg.norm(sd)) <= tol
+        np.testing.assert_allclose(s2.astype(F64), sd, atol=tol * 3)
+        # the move is the reflection: s1 + s is parallel to h
+        assert np.linalg.norm(np.cross(s1d + sd, hd)) <= tol * 10 * np.linalg.norm(hd)
+    z = np.zeros(3, dtype)
+    np.testing.assert_array_equal(O.overrelax_site(z, np.array([1, 0, 0], dtype)), [1, 0, 0])
+
+
+@pytest.mark.parametrize("dtype,tol", [(F32, 2e-6), (F64, 1e-13)])
+def test_overrelax_phase_conserves_energy(dtype, tol):
+    L = 12
+    s, J = inputs.random_state(L, 4, dtype)
+    E0 = O.energy(L, s, J)
+    s0 = s.copy()
+    O.sweep(L, 1, s, J, T=1.0, k=0, n_or=3, n_sweeps=4)
+    E1 = O.energy(L, s, J)
+    assert abs(E1 - E0) <= tol * abs(E0)  # microcanonical (§4)
+    assert np.abs(s - s0).max() > 0.1     # yet the configuration moved
+
+
+# ----------------------------------------------------------------- Metropolis
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_infinite_temperature_accepts_all_and_is_uniform(dtype):
+    L = 16
+    s, J = inputs.random_state(L, 8, dtype)
+    r = O.sweep(L, 3, s, J, T=np.inf, k=2, n_sweeps=2)
+    assert r["n_accepted"] == 2 * 2 * L ** 3
+    for a in range(3):
+        assert stats.kstest(s[a], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_zero_temperature_never_raises_energy(dtype):
+    L = 8
+    s, J = inputs.random_state(L, 21, dtype)
+    E = O.energy(L, s, J)
+    for n in range(5):
+        before = O.energy(L, s, J)
+        r = O.sweep(L, 5, s, J, T=1e-30, k=3, n_sweeps=1, sweep0=n, E=E)
+        E = r["E"]
+        after = O.energy(L, s, J)
+        assert after <= before + 1e-9 * abs(before)
+        assert r["n_accepted"] > 0
+    assert abs(E - O.energy(L, s, J)) <= (1e-5 if dtype == F32 else 1e-12) * abs(E)
+
+
+def _langevin_cdf(a):
+    return lambda c: (np.exp(a * (c - 1)) - np.exp(-2 * a)) / (1 - np.exp(-2 * a))
+
+
+@pytest.mark.parametrize("heat_bath,k", [(False, 64), (True, 1)])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_fixed_field_samples_boltzmann(heat_bath, k, dtype):
+    # Colour-0 sites see h = (0,0,6) in the first pass; after k hits their cosine to
+    # the field must follow the density exp(a c) on [-1, 1], a = 6 beta.
+    L = 24
+    T = 4.0
+    s, J = inputs.frozen_field_state(L, 31, dtype)
+    O.sweep(L, 77, s, J, T=T, k=k, n_sweeps=1, heat_bath=heat_bath)
+    c = s[2, inputs.colours(L) == 0].astype(F64)
+    a = 6.0 / T
+    assert stats.kstest(c, _langevin_cdf(a)).pvalue > 1e-3
+    mean_exact = 1 / np.tanh(a) - 1 / a
+    assert abs(c.mean() - mean_exact) < 5 * c.std() / np.sqrt(c.size)
+    # the azimuth stays uniform
+    phi = np.arctan2(s[1, inputs.colours(L) == 0], s[0, inputs.colours(L) == 0])
+    assert stats.kstest(phi, stats.uniform(loc=-np.pi, scale=2 * np.pi).cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("dtype,tol", [(F32, 1e-5), (F64, 1e-12)])
+@pytest.mark.parametrize("heat_bath", [False, True])
+def test_tracked_energy_equals_recomputed(dtype, tol, heat_bath):
+    L = 10
+    s, J = inputs.random_state(L, 12, dtype)
+    E = O.energy(L, s, J)
+    r = O.sweep(L, 9, s, J, T=0.7, k=4, n_or=1, n_sweeps=20, E=E, heat_bath=heat_bath)
+    assert abs(r["E"] - O.energy(L, s, J)) <= tol * abs(r["E"])
+
+
+def test_resume_is_exact():
+    L = 8
+    s, J = inputs.random_state(L, 1, F32)
+    a = s.copy()
+    O.sweep(L, 4, a, J, T=0.5, k=2, n_or=1, renorm_every=3, n_sweeps=9)
+    b = s.copy()
+    O.sweep(L, 4, b, J, T=0.5, k=2, n_or=1, renorm_every=3, n_sweeps=4)
+    O.sweep(L, 4, b, J, T=0.5, k=2, n_or=1, renorm_every=3, n_sweeps=5, sweep0=4)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_k_hits_equal_field_fixed_repeats():
+    # One k-hit Metropolis pass equals k independent single-site chains with the field
+    # frozen: check on a lattice where colour-1 spins are frozen along z and J = 1 by
+    # comparing the colour-0 result with a direct per-site evaluation of the hits.
+    L = 4
+    s, J = inputs.frozen_field_state(L, 3, F64)
+    s0 = s.copy()
+    O.sweep(L, 99, s, J, T=1.5, k=3, n_sweeps=1)
+    h = np.array([0.0, 0.0, 6.0])
+    c = inputs.colours(L)
+    for i in np.where(c == 0)[0]:
+        sig = s0[:, i].copy()
+        for j in range(3):
+            w = O.philox([[i, 0, j, O.TAG_MH]], 99)[0]
+            u = O.u01(w)
+            t = O.trial_spin(u[0], u[1], F64)
+            dE = float(sig @ h) - float(t @ h)
+            if dE <= 0 or u[2] < np.exp(-dE / 1.5):
+                sig = t
+        np.testing.assert_allclose(s[:, i], sig, atol=1e-14)
+
+
+# ---------------------------------------------------------- renormalisation
+def test_renormalise_unit_length():
+    s, _ = inputs.random_state(6, 2, F32)
+    s *= np.float32(1.01)
+    O.renormalise(s)
+    assert np.abs(np.linalg.norm(s.astype(F64), axis=0) - 1).max() < 2e-7
+
+
+# -------------------------------------------------------------------- overlap
+def test_overlap_closed_forms():
+    L = 6
+    a, _ = inputs.random_state(L, 1, F64)
+    Q, ma, mb = O.overlap(L, a, a)
+    assert abs(np.trace(Q) - 1) < 1e-14  # unit spins
+    # rotational covariance: b_i = R a_i gives Q(a, b) = Q(a, a) R^T  (index order)
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0], [0, 0, 1.0]])
+    R = R @ np.array([[1, 0, 0], [0, np.cos(0.3), -np.sin(0.3)], [0, np.sin(0.3), np.cos(0.3)]])
+    b = np.ascontiguousarray(R @ a)
+    Qab, ma2, mb2 = O.overlap(L, a, b)
+    np.testing.assert_allclose(Qab, Q @ R.T, atol=1e-14)
+    np.testing.assert_allclose(mb2, R @ ma2, atol=1e-14)
+    # uniform states: Q = n n'^T, m = n
+    n1, n2 = np.array([0.0, 0.6, 0.8]), np.array([1.0, 0.0, 0.0])
+    A = np.repeat(n1[:, None], L ** 3, axis=1)
+    B = np.repeat(n2[:, None], L ** 3, axis=1)
+    Q, ma, mb = O.overlap(L, A, B)
+    np.testing.assert_allclose(Q, np.outer(n1, n2), atol=1e-15)
+    np.testing.assert_allclose(ma, n1, atol=1e-15)
+
+
+# ---------------------------------------------------------- replica exchange
+def test_pt_swap_preserves_product_of_boltzmann_laws():
+    # Toy spectrum: energies 0..M-1 with unit degeneracy.  Draw each chain's energy
+    # from its slot's Boltzmann law, apply one exchange round, and check the energies
+    # now found in each slot still follow that slot's law (detailed balance).
+    rng = np.random.default_rng(5)
+    levels = np.arange(6.0)
+    betas = np.array([0.2, 0.5, 0.9, 1.4])
+    probs = [np.exp(-b * levels) / np.exp(-b * levels).sum() for b in betas]
+    n_trials = 40000
+    counts = np.zeros((len(betas), len(levels)))
+    for trial in range(n_trials):
+        E = np.array([rng.choice(levels, p=p) for p in probs])
+        chain_at_slot = np.arange(len(betas), dtype=np.int32)
+        O.pt_swap(betas, E, chain_at_slot, seed=17, stream_id=trial, round_=trial % 2)
+        for t in range(len(betas)):
+            counts[t, int(E[chain_at_slot[t]])] += 1
+    for t in range(len(betas)):
+        exp = probs[t] * n_trials
+        chi2 = ((counts[t] - exp) ** 2 / exp).sum()
+        assert stats.chi2.sf(chi2, len(levels) - 1) > 1e-4, (t, counts[t], exp)
+
+
+def test_pt_swap_equal_energies_always_swap():
+    chain = np.arange(5, dtype=np.int32)
+    n = O.pt_swap([1, 2, 3, 4, 5], np.zeros(5), chain, seed=1, stream_id=0, round_=0)
+    assert n == 2 and list(chain) == [1, 0, 3, 2, 4]
+    n = O.pt_swap([1, 2, 3, 4, 5], np.zeros(5), chain, seed=1, stream_id=0, round_=1)
+    assert n == 2 and list(chain) == [1, 3, 0, 4, 2]
+
+
+# ---------------------------------------------------------------- golden file
+def test_config1_golden_unchanged():
+    """The stored L=8 run (written by tests/golden/make_golden.py from the oracle)
+    still comes out bit for bit: guards the oracle against silent drift."""
+    import json
+    from tests.golden.make_golden import config1
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config1_L8_f64.json")) as f:
+        ref = json.load(f)
+    now = config1()
+    assert now["E0"] == ref["E0"]
+    for a, b in zip(now["sweeps"], ref["sweeps"]):
+        assert a == b
+    np.testing.assert_array_equal(np.array(now["final_spins"]), np.array(ref["final_spins"]))
+    # energy bookkeeping inside the stored run itself
+    for s in ref["sweeps"]:
+        assert abs(s["E_tracked"] - s["E_recomputed"]) <= 1e-12 * abs(s["E_recomputed"])
+
+
+def test_renormalise_schedule():
+    # renorm_every = R renormalises after sweep s exactly when (s+1) % R == 0.
+    # Over-relaxation keeps lengths, so stretched spins stay stretched until then.
+    L = 4
+    s, J = inputs.random_state(L, 6, F64)
+    s *= 1.25
+    for n in range(6):
+        O.sweep(L, 1, s, J, T=1.0, k=0, n_or=1, renorm_every=3, n_sweeps=1, sweep0=n)
+        norms = np.linalg.norm(s, axis=0)
+        want = 1.0 if (n + 1) % 3 == 0 else 1.25
+        np.testing.assert_allclose(norms, want, rtol=1e-12)
+        s *= 1.25 if (n + 1) % 3 == 0 else 1.0
