@@ -1,0 +1,125 @@
+/*
+ * hsg.h -- C interface of libhsg, the MI355X (gfx950) library for the checkerboard
+ * Monte Carlo sweep of the 3D Heisenberg spin glass of Bernaschi, Parisi & Parisi,
+ * "The Heisenberg spin glass model on GPU: myths and actual facts" (arXiv:1006.2566).
+ *
+ * Model (§2): spins sigma_i are 3-component unit vectors on an L x L x L lattice,
+ * periodic in x, y and z, site i = x + L*y + L*L*z; the couplings J_ij on the 3*L^3
+ * nearest-neighbour bonds are Gaussian with mean 0 and variance 1; the energy is
+ * H = -sum over bonds J_ij sigma_i . sigma_j (eq. 1, each bond once), and a site
+ * interacts with its six neighbours through the local field of eq. (2),
+ * h_i = sum_j J_ij sigma_j.  Dynamics (§4 and the methods §2 names): sites of one
+ * colour c = (x+y+z) & 1 share no bond and are updated together (the checkerboard);
+ * a sweep is a Monte Carlo phase (Metropolis with k hits per site, or heat bath),
+ * then n_or over-relaxation phases (reflection of sigma about h, §4), each phase
+ * being the colour-0 pass followed by the colour-1 pass.  Random numbers, which the
+ * paper leaves aside, come from Philox4x32-10 keyed by the lattice seed with counter
+ * (site, sweep, (phase << 16) | hit, stream tag).
+ *
+ * Conventions for every function:
+ *  - Return HSG_OK (0) or a negative HSG_E* code; never abort, never throw.  After an
+ *    error, hsg_last_error() returns a message (per calling thread).
+ *  - Buffers marked "device" are device memory the CALLER allocates and owns (the
+ *    Python binding uses torch tensors); the library allocates nothing persistent.
+ *  - Work is enqueued on the given HIP stream (hipStream_t passed as void*, NULL =
+ *    the default stream) and returns before it completes; results written to device
+ *    memory are valid once the stream has reached that point.
+ *  - Calls that share buffers must be ordered by the caller (one stream, or events).
+ *
+ * Internal layout ("colour-split", both spins and J): 6 planes of N/2 elements,
+ * plane (3*c + a) holds component (or bond direction) a of the colour-c sites, the
+ * site (x, y, z) of colour c sitting at index xh + (L/2)*(y + L*z) with
+ * x = 2*xh + ((y + z + c) & 1).  Use hsg_import / hsg_export to convert from / to
+ * the canonical layout (3 planes of N elements, element [a*N + i]).
+ */
+#ifndef HSG_H
+#define HSG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HSG_OK 0
+#define HSG_EINVAL (-1)      /* an argument is out of range or a required pointer is NULL */
+#define HSG_EDEVICE (-3)     /* a HIP call or kernel launch failed */
+#define HSG_EUNSUPPORTED (-4) /* valid request that this build does not implement */
+
+#define HSG_F32 0 /* binary32 spins and couplings */
+#define HSG_F64 1 /* binary64 spins and couplings */
+
+#define HSG_L_MAX 1290 /* largest L: N = L^3 < 2^31 keeps every site index in 32 bits */
+
+/* Sweep flags (hsg_sweep_params.flags). */
+#define HSG_HEAT_BATH 1 /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
+
+typedef struct hsg_lattice {
+  int32_t L;         /* even, 2 <= L <= HSG_L_MAX */
+  int32_t dtype;     /* HSG_F32 or HSG_F64 */
+  uint64_t seed;     /* Philox key of this lattice (init and Monte Carlo streams) */
+  uint64_t sweep;    /* index of the next sweep (Philox counter word); hsg_sweep adds n */
+  void *spins;       /* device, 3*L^3 elements of dtype, internal layout */
+  void *J;           /* device, 3*L^3 elements of dtype, internal layout */
+  double *E;         /* device, 1 double: the tracked energy H */
+  void *work;        /* device scratch of at least work_bytes from hsg_lattice_bytes */
+  size_t work_bytes; /* size of work in bytes */
+} hsg_lattice;
+
+typedef struct hsg_sweep_params {
+  double T;             /* temperature, > 0; INFINITY means beta = 0 */
+  int32_t k_hits;       /* Metropolis hits (or heat-bath draws) per site per sweep, >= 0 */
+  int32_t n_or;         /* over-relaxation phases per sweep, >= 0; k_hits + n_or >= 1 */
+  int32_t renorm_every; /* R > 0: after sweep s with (s+1) % R == 0 every spin is
+                           divided by its length; 0 = never */
+  int32_t flags;        /* 0 or HSG_HEAT_BATH */
+} hsg_sweep_params;
+
+/* Sizes of the three device buffers of an L^3 lattice of the given dtype.  Any
+ * output pointer may be NULL.  HSG_EINVAL for odd L, L < 2, L > HSG_L_MAX or an
+ * unknown dtype. */
+int hsg_lattice_bytes(int32_t L, int32_t dtype, size_t *spin_bytes, size_t *J_bytes,
+                      size_t *work_bytes);
+
+/* Random initial state from lat->seed (§2 model): spins uniform on the sphere,
+ * couplings N(0,1) by Box-Muller, both from Philox (stream tags 1 and 2, counter
+ * word 0 = canonical site index); then *lat->E = H and the scratch is cleared.
+ * lat->sweep is left as it is. */
+int hsg_init_lattice(hsg_lattice *lat, void *stream);
+
+/* Load a state given in canonical layout: canon_spins and canon_J are device
+ * arrays of 3*L^3 elements of lat->dtype ([a*N + i], J[d*N + i] = coupling of the
+ * bond (i, i + e_d)).  canon_J may be NULL to keep the couplings.  Sets *lat->E = H
+ * and clears the scratch.  Input and output must not overlap. */
+int hsg_import(hsg_lattice *lat, const void *canon_spins, const void *canon_J, void *stream);
+
+/* Write the state in canonical layout to device arrays of 3*L^3 elements;
+ * either output may be NULL. */
+int hsg_export(const hsg_lattice *lat, void *canon_spins, void *canon_J, void *stream);
+
+/* n_sweeps >= 0 sweeps of the dynamics described at the top of this file, starting at
+ * sweep index lat->sweep, which then advances by n_sweeps (the host-side field is
+ * updated when the call returns; the work itself is only enqueued).  *lat->E is
+ * advanced by the sum of accepted energy changes (binary64).  HSG_EINVAL also when
+ * the sweep index would pass 2^32. */
+int hsg_sweep(hsg_lattice *lat, const hsg_sweep_params *p, int32_t n_sweeps, void *stream);
+
+/* *out_dev = the energy H: the tracked value (recompute = 0) or a fresh binary64
+ * sum over all bonds (recompute != 0; deterministic order).  out_dev is device
+ * memory for one double. */
+int hsg_energy(const hsg_lattice *lat, int32_t recompute, double *out_dev, void *stream);
+
+/* Overlap between two configurations of the same L and dtype (binary64 sums):
+ * out_dev[3*mu + nu] = (1/N) sum_i a_i^mu b_i^nu for mu, nu in {x,y,z}, then the
+ * magnetisations out_dev[9..11] = (1/N) sum_i a_i, out_dev[12..14] = (1/N) sum_i b_i.
+ * out_dev is device memory for 15 doubles.  a's work buffer is used as scratch. */
+int hsg_overlap(const hsg_lattice *a, const hsg_lattice *b, double *out_dev, void *stream);
+
+/* Message describing the last error returned to this thread ("" if none). */
+const char *hsg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSG_H */

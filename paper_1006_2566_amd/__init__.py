@@ -1,0 +1,194 @@
+"""Heisenberg spin-glass Monte Carlo on AMD MI355X (gfx950).
+
+Python binding of ``libhsg.so`` (C interface in ``include/hsg.h``).  This module
+only marshals arguments: every step of a sweep runs in the HIP kernels of the
+library.  PyTorch provides device memory and the current HIP stream.
+
+The model and dynamics are those of Bernaschi, Parisi & Parisi, "The Heisenberg spin
+glass model on GPU: myths and actual facts" (arXiv:1006.2566): 3-component unit spins
+on an L^3 periodic lattice with Gaussian couplings (§2, eqs. 1-2), checkerboard
+updates with over-relaxation (§4), plus the Metropolis / heat-bath moves the paper
+names, driven by a Philox counter-based generator.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+__all__ = ["Lattice", "HsgError", "lib", "lattice_bytes", "LIB_PATH"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhsg.so")
+
+HSG_F32, HSG_F64 = 0, 1
+HSG_HEAT_BATH = 1
+L_MAX = 1290
+
+
+class HsgError(RuntimeError):
+    """A libhsg call returned an error status."""
+
+    def __init__(self, code: int, message: str):
+        super().__init__(f"libhsg error {code}: {message}")
+        self.code = code
+
+
+class _Lattice(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int32), ("dtype", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("sweep", ctypes.c_uint64), ("spins", ctypes.c_void_p), ("J", ctypes.c_void_p),
+                ("E", ctypes.c_void_p), ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t)]
+
+
+class _SweepParams(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("k_hits", ctypes.c_int32), ("n_or", ctypes.c_int32),
+                ("renorm_every", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded HIP library.  Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, SZ = ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_size_t)
+        LP = ctypes.POINTER(_Lattice)
+        L.hsg_lattice_bytes.argtypes = [I32, I32, SZ, SZ, SZ]
+        L.hsg_init_lattice.argtypes = [LP, P]
+        L.hsg_import.argtypes = [LP, P, P, P]
+        L.hsg_export.argtypes = [LP, P, P, P]
+        L.hsg_sweep.argtypes = [LP, ctypes.POINTER(_SweepParams), I32, P]
+        L.hsg_energy.argtypes = [LP, I32, P, P]
+        L.hsg_overlap.argtypes = [LP, LP, P, P]
+        L.hsg_last_error.restype = ctypes.c_char_p
+        for name in ("hsg_lattice_bytes", "hsg_init_lattice", "hsg_import", "hsg_export",
+                     "hsg_sweep", "hsg_energy", "hsg_overlap"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def check(rc: int) -> None:
+    if rc != 0:
+        raise HsgError(rc, lib().hsg_last_error().decode())
+
+
+def _dtype_code(dtype: torch.dtype) -> int:
+    if dtype == torch.float32:
+        return HSG_F32
+    if dtype == torch.float64:
+        return HSG_F64
+    raise TypeError(f"spins are float32 or float64, not {dtype}")
+
+
+def lattice_bytes(L: int, dtype: torch.dtype = torch.float32) -> tuple[int, int, int]:
+    """(spin_bytes, J_bytes, work_bytes) of an L^3 lattice."""
+    s, j, w = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    check(lib().hsg_lattice_bytes(L, _dtype_code(dtype), ctypes.byref(s), ctypes.byref(j),
+                                  ctypes.byref(w)))
+    return s.value, j.value, w.value
+
+
+def _stream(stream=None) -> ctypes.c_void_p:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """One L^3 lattice resident on the GPU (colour-split layout, see include/hsg.h).
+
+    ``init="random"`` draws the Philox initial state from ``seed``; ``init=None``
+    leaves the buffers for :meth:`load`.
+    """
+
+    def __init__(self, L: int, dtype: torch.dtype = torch.float32, seed: int = 1,
+                 device: str | torch.device = "cuda", init: str | None = "random",
+                 stream=None):
+        spin_b, j_b, work_b = lattice_bytes(L, dtype)
+        self.L, self.dtype, self.device = L, dtype, torch.device(device)
+        n = 3 * L ** 3
+        self.spins = torch.empty(n, dtype=dtype, device=self.device)
+        self.J = torch.empty(n, dtype=dtype, device=self.device)
+        self.E = torch.zeros(1, dtype=torch.float64, device=self.device)
+        self.work = torch.zeros(work_b, dtype=torch.uint8, device=self.device)
+        self._d = _Lattice(L, _dtype_code(dtype), seed & (2 ** 64 - 1), 0, self.spins.data_ptr(),
+                           self.J.data_ptr(), self.E.data_ptr(), self.work.data_ptr(), work_b)
+        if init == "random":
+            self.init_random(stream)
+
+    # ------------------------------------------------------------------ state
+    @property
+    def N(self) -> int:
+        return self.L ** 3
+
+    @property
+    def seed(self) -> int:
+        return self._d.seed
+
+    @property
+    def sweep_index(self) -> int:
+        return self._d.sweep
+
+    @sweep_index.setter
+    def sweep_index(self, value: int) -> None:
+        self._d.sweep = int(value)
+
+    def init_random(self, stream=None) -> None:
+        check(lib().hsg_init_lattice(ctypes.byref(self._d), _stream(stream)))
+
+    def load(self, spins, J=None, stream=None) -> None:
+        """Load canonical-layout spins (and couplings), shape (3, N), any device."""
+        s = torch.as_tensor(spins).to(device=self.device, dtype=self.dtype).contiguous()
+        assert s.numel() == 3 * self.N
+        j = None
+        if J is not None:
+            j = torch.as_tensor(J).to(device=self.device, dtype=self.dtype).contiguous()
+            assert j.numel() == 3 * self.N
+        check(lib().hsg_import(ctypes.byref(self._d), _ptr(s), _ptr(j) if j is not None else None,
+                               _stream(stream)))
+        torch.cuda.current_stream().synchronize() if stream is None else stream.synchronize()
+
+    def export(self, stream=None) -> tuple[torch.Tensor, torch.Tensor]:
+        """Canonical-layout (spins, J), each of shape (3, N), on the device."""
+        s = torch.empty((3, self.N), dtype=self.dtype, device=self.device)
+        j = torch.empty((3, self.N), dtype=self.dtype, device=self.device)
+        check(lib().hsg_export(ctypes.byref(self._d), _ptr(s), _ptr(j), _stream(stream)))
+        return s, j
+
+    # --------------------------------------------------------------- dynamics
+    def sweep(self, T: float, k: int = 1, n_or: int = 0, renorm_every: int = 0,
+              n_sweeps: int = 1, heat_bath: bool = False, stream=None) -> None:
+        p = _SweepParams(float(T), int(k), int(n_or), int(renorm_every),
+                         HSG_HEAT_BATH if heat_bath else 0)
+        check(lib().hsg_sweep(ctypes.byref(self._d), ctypes.byref(p), int(n_sweeps),
+                              _stream(stream)))
+
+    # ---------------------------------------------------------- observables
+    def energy(self, recompute: bool = False, stream=None) -> torch.Tensor:
+        """Energy H as a 1-element float64 device tensor (tracked or recomputed)."""
+        out = torch.empty(1, dtype=torch.float64, device=self.device)
+        check(lib().hsg_energy(ctypes.byref(self._d), int(bool(recompute)), _ptr(out),
+                               _stream(stream)))
+        return out
+
+    def overlap(self, other: "Lattice", stream=None) -> torch.Tensor:
+        """15 float64 values: Q[3x3] row-major, then m_self[3], m_other[3]."""
+        out = torch.empty(15, dtype=torch.float64, device=self.device)
+        check(lib().hsg_overlap(ctypes.byref(self._d), ctypes.byref(other._d), _ptr(out),
+                                _stream(stream)))
+        return out
+
+
+def beta(T: float) -> float:
+    return 0.0 if math.isinf(T) else 1.0 / T

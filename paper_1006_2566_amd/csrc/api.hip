@@ -1,0 +1,215 @@
+// C interface of libhsg (declared and documented in include/hsg.h): argument
+// validation, the sweep schedule, and error reporting.  Every entry point returns a
+// status code and never throws; kernels are only enqueued on the caller's stream.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include "hsg.h"
+#include "hsg_internal.h"
+
+namespace {
+
+thread_local char g_last_error[512] = "";
+
+int fail(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_last_error, sizeof g_last_error, fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+int device_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return HSG_OK;
+  return fail(HSG_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+int check_dims(int32_t L, int32_t dtype) {
+  if (L < 2 || L > HSG_L_MAX || (L & 1))
+    return fail(HSG_EINVAL, "L must be even with 2 <= L <= %d (got %d)", HSG_L_MAX, (int)L);
+  if (dtype != HSG_F32 && dtype != HSG_F64)
+    return fail(HSG_EINVAL, "dtype must be HSG_F32 or HSG_F64 (got %d)", (int)dtype);
+  return HSG_OK;
+}
+
+int check_lattice(const hsg_lattice* lat) {
+  if (!lat) return fail(HSG_EINVAL, "lattice descriptor is NULL");
+  int rc = check_dims(lat->L, lat->dtype);
+  if (rc) return rc;
+  if (!lat->spins || !lat->J || !lat->E || !lat->work)
+    return fail(HSG_EINVAL, "lattice buffers spins, J, E and work must all be set");
+  const size_t need = hsg::work_bytes_for(lat->L);
+  if (lat->work_bytes < need)
+    return fail(HSG_EINVAL, "work buffer too small: %zu bytes, need %zu", lat->work_bytes, need);
+  return HSG_OK;
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+template <typename R>
+int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
+  using namespace hsg;
+  const Geometry g = pass_geometry(lat->L);
+  const int64_t Nh = (int64_t)lat->L * lat->L * lat->L / 2;
+  PassArgs<R> a{};
+  a.spins = planes_of<R>(lat->spins, Nh);
+  a.J = planes_of<R>(lat->J, Nh);
+  a.partials = pass_partials(lat->work);
+  a.beta = (R)(1.0 / p->T);
+  a.seed_lo = (uint32_t)lat->seed;
+  a.seed_hi = (uint32_t)(lat->seed >> 32);
+  a.k_hits = p->k_hits;
+  a.g = g;
+  const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
+  for (int32_t n = 0; n < n_sweeps; ++n) {
+    const uint64_t sweep = lat->sweep + (uint64_t)n;
+    a.sweep = (uint32_t)sweep;
+    for (int32_t phase = 0; phase <= p->n_or; ++phase) {
+      if (phase == 0 && p->k_hits == 0) continue;
+      a.phase = (uint32_t)phase;
+      for (int32_t colour = 0; colour < 2; ++colour) {
+        a.colour = colour;
+        int rc = device_status(
+            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, a, st), "colour pass");
+        if (rc) return rc;
+      }
+    }
+    if (p->renorm_every > 0 && (sweep + 1) % (uint64_t)p->renorm_every == 0) {
+      int rc = device_status(launch_renormalise<R>(lat->L, lat->spins, st), "renormalise");
+      if (rc) return rc;
+    }
+  }
+  if (n_sweeps > 0 && p->k_hits > 0) {
+    int rc = device_status(launch_fold_partials(a.partials, g.n_blocks, lat->E, st), "fold");
+    if (rc) return rc;
+  }
+  return HSG_OK;
+}
+
+// Clears the pass partials and sets *E = H.
+template <typename R>
+int reset_energy(hsg_lattice* lat, hipStream_t st) {
+  using namespace hsg;
+  int rc = device_status(launch_zero(pass_partials(lat->work), pass_geometry(lat->L).n_blocks, st),
+                         "clear scratch");
+  if (rc) return rc;
+  return device_status(launch_energy<R>(lat->L, lat->spins, lat->J,
+                                        reduce_partials(lat->work, lat->L), lat->E, st),
+                       "energy");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hsg_last_error(void) { return g_last_error; }
+
+int hsg_lattice_bytes(int32_t L, int32_t dtype, size_t* spin_bytes, size_t* J_bytes,
+                      size_t* work_bytes) {
+  int rc = check_dims(L, dtype);
+  if (rc) return rc;
+  const size_t elem = dtype == HSG_F32 ? 4 : 8;
+  const size_t n = (size_t)3 * L * L * L;
+  if (spin_bytes) *spin_bytes = n * elem;
+  if (J_bytes) *J_bytes = n * elem;
+  if (work_bytes) *work_bytes = hsg::work_bytes_for(L);
+  return HSG_OK;
+}
+
+int hsg_init_lattice(hsg_lattice* lat, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  if (lat->dtype == HSG_F32) {
+    rc = device_status(hsg::launch_init<float>(lat->L, lat->seed, lat->spins, lat->J, st), "init");
+    return rc ? rc : reset_energy<float>(lat, st);
+  }
+  rc = device_status(hsg::launch_init<double>(lat->L, lat->seed, lat->spins, lat->J, st), "init");
+  return rc ? rc : reset_energy<double>(lat, st);
+}
+
+int hsg_import(hsg_lattice* lat, const void* canon_spins, const void* canon_J, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!canon_spins) return fail(HSG_EINVAL, "canon_spins is NULL");
+  hipStream_t st = as_stream(stream);
+  if (lat->dtype == HSG_F32) {
+    rc = device_status(hsg::launch_import<float>(lat->L, (const float*)canon_spins,
+                                                 (const float*)canon_J, lat->spins, lat->J, st),
+                       "import");
+    return rc ? rc : reset_energy<float>(lat, st);
+  }
+  rc = device_status(hsg::launch_import<double>(lat->L, (const double*)canon_spins,
+                                                (const double*)canon_J, lat->spins, lat->J, st),
+                     "import");
+  return rc ? rc : reset_energy<double>(lat, st);
+}
+
+int hsg_export(const hsg_lattice* lat, void* canon_spins, void* canon_J, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!canon_spins && !canon_J) return HSG_OK;
+  hipStream_t st = as_stream(stream);
+  if (lat->dtype == HSG_F32)
+    return device_status(hsg::launch_export<float>(lat->L, lat->spins, lat->J, (float*)canon_spins,
+                                                   (float*)canon_J, st),
+                         "export");
+  return device_status(hsg::launch_export<double>(lat->L, lat->spins, lat->J,
+                                                  (double*)canon_spins, (double*)canon_J, st),
+                       "export");
+}
+
+int hsg_sweep(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!p) return fail(HSG_EINVAL, "sweep parameters are NULL");
+  if (!(p->T > 0.0)) return fail(HSG_EINVAL, "T must be > 0 (INFINITY for beta = 0), got %g", p->T);
+  if (p->k_hits < 0 || p->n_or < 0 || p->k_hits + p->n_or < 1)
+    return fail(HSG_EINVAL, "need k_hits >= 0, n_or >= 0 and k_hits + n_or >= 1");
+  if (p->n_or > 0x7FFF || p->k_hits > 0xFFFF)
+    return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
+  if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
+  if (p->flags & ~HSG_HEAT_BATH) return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
+  if (n_sweeps < 0) return fail(HSG_EINVAL, "n_sweeps must be >= 0");
+  if (lat->sweep + (uint64_t)n_sweeps > 0x100000000ull)
+    return fail(HSG_EINVAL, "sweep index would pass 2^32");
+  hipStream_t st = as_stream(stream);
+  rc = lat->dtype == HSG_F32 ? sweep_impl<float>(lat, p, n_sweeps, st)
+                             : sweep_impl<double>(lat, p, n_sweeps, st);
+  if (rc == HSG_OK) lat->sweep += (uint64_t)n_sweeps;
+  return rc;
+}
+
+int hsg_energy(const hsg_lattice* lat, int32_t recompute, double* out_dev, void* stream) {
+  int rc = check_lattice(lat);
+  if (rc) return rc;
+  if (!out_dev) return fail(HSG_EINVAL, "out_dev is NULL");
+  hipStream_t st = as_stream(stream);
+  if (!recompute) return device_status(hsg::launch_copy_double(lat->E, out_dev, st), "energy copy");
+  double* part = hsg::reduce_partials(lat->work, lat->L);
+  if (lat->dtype == HSG_F32)
+    return device_status(hsg::launch_energy<float>(lat->L, lat->spins, lat->J, part, out_dev, st),
+                         "energy");
+  return device_status(hsg::launch_energy<double>(lat->L, lat->spins, lat->J, part, out_dev, st),
+                       "energy");
+}
+
+int hsg_overlap(const hsg_lattice* a, const hsg_lattice* b, double* out_dev, void* stream) {
+  int rc = check_lattice(a);
+  if (rc) return rc;
+  rc = check_lattice(b);
+  if (rc) return rc;
+  if (a->L != b->L || a->dtype != b->dtype)
+    return fail(HSG_EINVAL, "overlap needs two lattices of the same L and dtype");
+  if (!out_dev) return fail(HSG_EINVAL, "out_dev is NULL");
+  hipStream_t st = as_stream(stream);
+  double* part = hsg::reduce_partials(a->work, a->L);
+  if (a->dtype == HSG_F32)
+    return device_status(hsg::launch_overlap<float>(a->L, a->spins, b->spins, part, out_dev, st),
+                         "overlap");
+  return device_status(hsg::launch_overlap<double>(a->L, a->spins, b->spins, part, out_dev, st),
+                       "overlap");
+}
+
+}  // extern "C"

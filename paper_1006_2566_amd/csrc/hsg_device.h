@@ -1,0 +1,220 @@
+// Device-side arithmetic shared by the sweep, init and batch kernels (gfx950).
+//
+// Every floating-point step is spelled out (explicit fused multiply-adds, the
+// library is built with -ffp-contract=off, division and square root correctly
+// rounded), so that a site update is a fixed function of its inputs and random
+// draws: the GPU result is reproducible bit for bit across launch shapes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hsg {
+
+// Philox stream tags: fourth word of the counter.
+enum : uint32_t { kTagMetropolis = 0, kTagInitSpin = 1, kTagInitJ = 2, kTagSwap = 3,
+                  kTagHeatBath = 5 };
+
+struct Word4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+// Philox4x32-10 (Salmon et al., SC'11).  Each round takes two 32x32->64 products
+// of counter words 0 and 2 with the round multipliers and mixes their halves with
+// words 1 and 3 and the key; the key advances by the Weyl constants between rounds.
+// A product of a wave-uniform word stays on the scalar unit, so with a uniform key
+// and uniform counter words 1..3 the first two rounds cost one vector product each.
+__device__ __forceinline__ Word4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                          uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
+    const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
+    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)b;
+    c3 = (uint32_t)a;
+    c0 = n0;
+    c2 = n2;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return Word4{c0, c1, c2, c3};
+}
+
+// Uniform in (0,1): the top 23 bits of w as an odd multiple of 2^-24.  Exact in
+// binary32 and binary64 (the same value in both precisions).
+template <typename R>
+__device__ __forceinline__ R unit_uniform(uint32_t w) {
+  const uint32_t odd = ((w >> 9) << 1) | 1u;  // < 2^24, exactly representable
+  return (R)odd * (R)0x1p-24;
+}
+
+template <typename R>
+struct Trig;
+
+// sin/cos(pi r / 2) on r in [-1/2, 1/2]: Taylor polynomials in r (correctly rounded
+// coefficients (+-)(pi/2)^k / k!), Horner with fused multiply-adds.
+template <>
+struct Trig<float> {
+  __device__ __forceinline__ static void eval(float r, float& s, float& c) {
+    const float r2 = r * r;
+    float p = 0x1.507834p-13f;          // r^9
+    p = fmaf(p, r2, -0x1.32d2ccp-8f);   // r^7
+    p = fmaf(p, r2, 0x1.466bc6p-4f);    // r^5
+    p = fmaf(p, r2, -0x1.4abbcep-1f);   // r^3
+    p = fmaf(p, r2, 0x1.921fb6p+0f);    // r^1
+    s = p * r;
+    float q = -0x1.a6d1f2p-16f;         // r^10
+    q = fmaf(q, r2, 0x1.e1f506p-11f);   // r^8
+    q = fmaf(q, r2, -0x1.55d3c8p-6f);   // r^6
+    q = fmaf(q, r2, 0x1.03c1f0p-2f);    // r^4
+    q = fmaf(q, r2, -0x1.3bd3ccp+0f);   // r^2
+    c = fmaf(q, r2, 1.0f);              // r^0
+  }
+};
+
+template <>
+struct Trig<double> {
+  __device__ __forceinline__ static void eval(double r, double& s, double& c) {
+    const double r2 = r * r;
+    double p = 0x1.aaec32af93359p-38;      // r^17
+    p = fma(p, r2, -0x1.6fadb9f155744p-31);  // r^15
+    p = fma(p, r2, 0x1.e8f434d018d63p-25);   // r^13
+    p = fma(p, r2, -0x1.e3074fde8871fp-19);  // r^11
+    p = fma(p, r2, 0x1.50783487ee782p-13);   // r^9
+    p = fma(p, r2, -0x1.32d2cce62bd86p-8);   // r^7
+    p = fma(p, r2, 0x1.466bc6775aae2p-4);    // r^5
+    p = fma(p, r2, -0x1.4abbce625be53p-1);   // r^3
+    p = fma(p, r2, 0x1.921fb54442d18p+0);    // r^1
+    s = p * r;
+    double q = 0x1.20c62c2f2d7f5p-34;       // r^16
+    q = fma(q, r2, -0x1.b6e24f44b128fp-28);  // r^14
+    q = fma(q, r2, 0x1.f9d38a3763cc3p-22);   // r^12
+    q = fma(q, r2, -0x1.a6d1f2a204a8cp-16);  // r^10
+    q = fma(q, r2, 0x1.e1f506891babbp-11);   // r^8
+    q = fma(q, r2, -0x1.55d3c7e3cbffap-6);   // r^6
+    q = fma(q, r2, 0x1.03c1f081b5ac4p-2);    // r^4
+    q = fma(q, r2, -0x1.3bd3cc9be45dep+0);   // r^2
+    c = fma(q, r2, 1.0);                     // r^0
+  }
+};
+
+__device__ __forceinline__ float dev_fma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double dev_fma(double a, double b, double c) { return fma(a, b, c); }
+// sqrtf is correctly rounded under -fhip-fp32-correctly-rounded-divide-sqrt (the
+// residual-checked expansion around v_sqrt_f32); __fsqrt_rn is not on this toolchain.
+__device__ __forceinline__ float dev_sqrt(float a) { return sqrtf(a); }
+__device__ __forceinline__ double dev_sqrt(double a) { return sqrt(a); }
+__device__ __forceinline__ float dev_div(float a, float b) { return __fdiv_rn(a, b); }
+__device__ __forceinline__ double dev_div(double a, double b) { return __ddiv_rn(a, b); }
+__device__ __forceinline__ float dev_exp(float a) { return expf(a); }
+__device__ __forceinline__ double dev_exp(double a) { return exp(a); }
+__device__ __forceinline__ float dev_log(float a) { return logf(a); }
+__device__ __forceinline__ double dev_log(double a) { return log(a); }
+__device__ __forceinline__ float dev_log1p(float a) { return log1pf(a); }
+__device__ __forceinline__ double dev_log1p(double a) { return log1p(a); }
+__device__ __forceinline__ float dev_expm1(float a) { return expm1f(a); }
+__device__ __forceinline__ double dev_expm1(double a) { return expm1(a); }
+__device__ __forceinline__ float dev_rint(float a) { return rintf(a); }
+__device__ __forceinline__ double dev_rint(double a) { return rint(a); }
+
+// (sin, cos) of 2 pi u for an exact uniform u.  t = 4u splits exactly into its
+// nearest integer q (t is never a half-integer) and r = t - q, 2 pi u = (pi/2)(q + r);
+// the quadrant q mod 4 rotates (sin, cos) of (pi/2) r.
+template <typename R>
+__device__ __forceinline__ void sincos_2pi(R u, R& s_out, R& c_out) {
+  const R t = u * (R)4;
+  const R q = dev_rint(t);
+  const R r = t - q;
+  R s, c;
+  Trig<R>::eval(r, s, c);
+  const int quadrant = ((int)q) & 3;
+  const R cq = (quadrant & 1) ? s : c;  // quadrants 1, 3 exchange the pair
+  const R sq = (quadrant & 1) ? c : s;
+  c_out = (quadrant == 1 || quadrant == 2) ? -cq : cq;
+  s_out = (quadrant >= 2) ? -sq : sq;
+}
+
+template <typename R>
+struct Vec3 {
+  R x, y, z;
+};
+
+template <typename R>
+__device__ __forceinline__ R dot3(const Vec3<R>& a, const Vec3<R>& b) {
+  return dev_fma(a.z, b.z, dev_fma(a.y, b.y, a.x * b.x));
+}
+
+// Point uniform on the unit sphere: z = 2 u0 - 1 is uniform on [-1, 1] (exact),
+// the azimuth 2 pi u1 is uniform and independent, rho = sqrt(1 - z^2) rounded once
+// inside the root.
+template <typename R>
+__device__ __forceinline__ Vec3<R> sphere_point(R u0, R u1) {
+  const R z = (R)2 * u0 - (R)1;
+  const R rho = dev_sqrt(dev_fma(-z, z, (R)1));
+  R s, c;
+  sincos_2pi(u1, s, c);
+  return Vec3<R>{rho * c, rho * s, z};
+}
+
+// Exact draw from the conditional law exp(beta sigma.h) on the sphere.  With
+// a = beta |h|, the cosine to the field is c = 1 + log1p(-(1-u0)(1-e^{-2a}))/a
+// (c = 2 u0 - 1 for a = 0), the azimuth is 2 pi u1, and the tangent frame about
+// n = h/|h| is the branch-free orthonormal basis of Duff et al. (JCGT 2017).
+template <typename R>
+__device__ __forceinline__ Vec3<R> heat_bath_point(const Vec3<R>& h, R beta, R u0, R u1) {
+  const R hh = dot3(h, h);
+  const R hn = dev_sqrt(hh);
+  const R a = beta * hn;
+  R c;
+  if (a > (R)0) {
+    const R one_m_u = (R)1 - u0;
+    c = (R)1 + dev_div(dev_log1p(-(one_m_u * -dev_expm1((R)-2 * a))), a);
+  } else {
+    c = (R)2 * u0 - (R)1;
+  }
+  c = c > (R)1 ? (R)1 : c;
+  c = c < (R)-1 ? (R)-1 : c;
+  const R rho = dev_sqrt(dev_fma(-c, c, (R)1));
+  R sn, cs;
+  sincos_2pi(u1, sn, cs);
+  if (!(hh > (R)0)) return Vec3<R>{rho * cs, rho * sn, c};
+  const Vec3<R> n{dev_div(h.x, hn), dev_div(h.y, hn), dev_div(h.z, hn)};
+  const R sgn = n.z >= (R)0 ? (R)1 : (R)-1;
+  const R ia = dev_div((R)-1, sgn + n.z);
+  const R b = n.x * n.y * ia;
+  const Vec3<R> e1{dev_fma(sgn * n.x * n.x, ia, (R)1), sgn * b, -sgn * n.x};
+  const Vec3<R> e2{b, dev_fma(n.y * n.y, ia, sgn), -n.y};
+  const R px = rho * cs, py = rho * sn;
+  return Vec3<R>{dev_fma(c, n.x, dev_fma(px, e1.x, py * e2.x)),
+                 dev_fma(c, n.y, dev_fma(px, e1.y, py * e2.y)),
+                 dev_fma(c, n.z, dev_fma(px, e1.z, py * e2.z))};
+}
+
+// Reflection of s about the field direction (over-relaxation): the largest move
+// that keeps -s.h; a zero field leaves s unchanged.
+template <typename R>
+__device__ __forceinline__ Vec3<R> reflect(const Vec3<R>& s, const Vec3<R>& h) {
+  const R hh = dot3(h, h);
+  const R sh = dot3(s, h);
+  const R f = dev_div(sh + sh, hh);
+  const bool ok = hh > (R)0;
+  return Vec3<R>{ok ? dev_fma(f, h.x, -s.x) : s.x, ok ? dev_fma(f, h.y, -s.y) : s.y,
+                 ok ? dev_fma(f, h.z, -s.z) : s.z};
+}
+
+// Sum of a double across the 64 lanes of a wavefront (butterfly; every lane ends
+// with the same value).  Within rows of 16 lanes the exchanges use DPP
+// (quad_perm and row mirrors); across rows they use ds_swizzle-free lane shuffles.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += __shfl_xor(v, 1);
+  v += __shfl_xor(v, 2);
+  v += __shfl_xor(v, 4);
+  v += __shfl_xor(v, 8);
+  v += __shfl_xor(v, 16);
+  v += __shfl_xor(v, 32);
+  return v;
+}
+
+}  // namespace hsg

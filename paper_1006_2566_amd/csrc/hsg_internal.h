@@ -1,0 +1,94 @@
+// Host-side internals of libhsg: launch geometry, kernel argument blocks and the
+// launchers each kernel file exports to the C interface in api.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace hsg {
+
+// A colour pass covers the N/2 sites of one colour, stored as L planes (z) of L rows
+// (y) of L/2 sites (xh).  Each workgroup takes a BX x BY x BZ tile of (xh, y, z);
+// BX is one wavefront wide when L/2 allows it, so a wave reads whole row segments.
+struct Geometry {
+  int32_t L, Lh;
+  int32_t bx_log, by_log, bz_log;     // tile extents are 1 << *_log
+  int32_t tiles_x, tiles_y, tiles_z;  // tiles along xh, y, z
+  int32_t n_blocks;                   // tiles_x * tiles_y * tiles_z
+  int32_t threads;                    // BX * BY * BZ (<= 256)
+};
+
+Geometry pass_geometry(int32_t L);
+
+// Blocks of the fixed-size grid used by the energy and overlap reductions.
+constexpr int kReduceBlocks = 1024;
+constexpr int kReduceThreads = 256;
+constexpr int kReduceSlots = 16;  // doubles per block partial (overlap needs 15)
+
+// Scratch layout of hsg_lattice.work (bytes):
+//   [0, 256)                              reserved
+//   [256, 256 + 8*n_blocks)               per-tile energy-change partials of the passes
+//   [.., + 8*kReduceBlocks*kReduceSlots)  per-block partials of energy / overlap
+size_t work_bytes_for(int32_t L);
+inline double* pass_partials(void* work) { return (double*)((char*)work + 256); }
+inline double* reduce_partials(void* work, int32_t L) {
+  return pass_partials(work) + pass_geometry(L).n_blocks;
+}
+
+// Pointers of the six planes (3 components x 2 colours) of a colour-split array.
+template <typename R>
+struct Planes {
+  R* p[6];
+};
+
+template <typename R>
+inline Planes<R> planes_of(void* base, int64_t half_sites) {
+  Planes<R> out;
+  for (int k = 0; k < 6; ++k) out.p[k] = (R*)base + (int64_t)k * half_sites;
+  return out;
+}
+
+enum class PassMode : int { Metropolis = 0, OverRelax = 1, HeatBath = 2 };
+
+template <typename R>
+struct PassArgs {
+  Planes<R> spins;   // colour-split spins
+  Planes<R> J;       // colour-split couplings
+  double* partials;  // one double per tile (Metropolis / heat bath only)
+  R beta;
+  uint32_t seed_lo, seed_hi;
+  uint32_t sweep;
+  uint32_t phase;
+  int32_t k_hits;
+  int32_t colour;
+  Geometry g;
+};
+
+template <typename R>
+hipError_t launch_colour_pass(PassMode mode, const PassArgs<R>& a, hipStream_t stream);
+
+// *E += sum of the n partials (fixed order); the partials are then zeroed.
+hipError_t launch_fold_partials(double* partials, int32_t n, double* E, hipStream_t stream);
+
+template <typename R>
+hipError_t launch_init(int32_t L, uint64_t seed, void* spins, void* J, hipStream_t stream);
+template <typename R>
+hipError_t launch_import(int32_t L, const R* canon_spins, const R* canon_J, void* spins,
+                         void* J, hipStream_t stream);
+template <typename R>
+hipError_t launch_export(int32_t L, const void* spins, const void* J, R* canon_spins,
+                         R* canon_J, hipStream_t stream);
+template <typename R>
+hipError_t launch_renormalise(int32_t L, void* spins, hipStream_t stream);
+// out[0] = H (recomputed, binary64).
+template <typename R>
+hipError_t launch_energy(int32_t L, const void* spins, const void* J, double* partials,
+                         double* out, hipStream_t stream);
+template <typename R>
+hipError_t launch_overlap(int32_t L, const void* a, const void* b, double* partials,
+                          double* out, hipStream_t stream);
+hipError_t launch_zero(double* p, int64_t n, hipStream_t stream);
+hipError_t launch_copy_double(const double* src, double* dst, hipStream_t stream);
+
+}  // namespace hsg

@@ -1,0 +1,118 @@
+"""The C interface without a GPU: the library loads, exports every function the
+header declares, sizes buffers, and rejects invalid arguments with an error code
+(no call here reaches a kernel)."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hsg.h")
+
+
+@pytest.fixture(scope="module")
+def hsg():
+    import paper_1006_2566_amd as m
+    if not os.path.exists(m.LIB_PATH):
+        from paper_1006_2566_amd import build
+        build.build()
+    m.lib()
+    return m
+
+
+def declared_functions() -> list[str]:
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hsg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_every_declared_symbol_is_exported(hsg):
+    names = declared_functions()
+    assert "hsg_sweep" in names and "hsg_init_lattice" in names
+    assert "hsg_energy" in names and "hsg_overlap" in names
+    lib = hsg.lib()
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_lattice_bytes(hsg):
+    s, j, w = hsg.lattice_bytes(8)
+    assert s == j == 3 * 512 * 4 and w > 0
+    s64, j64, w64 = hsg.lattice_bytes(8, hsg_dtype := __import__("torch").float64)
+    assert s64 == j64 == 3 * 512 * 8 and w64 == w
+    s, _, _ = hsg.lattice_bytes(1290)
+    assert s == 3 * 1290 ** 3 * 4
+
+
+@pytest.mark.parametrize("L", [0, 1, 3, 7, -2, 1292, 2 ** 20])
+def test_lattice_bytes_rejects_bad_L(hsg, L):
+    lib = hsg.lib()
+    rc = lib.hsg_lattice_bytes(L, 0, None, None, None)
+    assert rc == -1
+    assert b"L must be even" in lib.hsg_last_error()
+
+
+def test_lattice_bytes_rejects_bad_dtype(hsg):
+    assert hsg.lib().hsg_lattice_bytes(8, 7, None, None, None) == -1
+
+
+def _desc(hsg, **kw):
+    d = hsg._Lattice(8, 0, 1, 0, 0x1000, 0x2000, 0x3000, 0x4000, hsg.lattice_bytes(8)[2])
+    for k, v in kw.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_null_and_missing_buffers_rejected(hsg):
+    lib = hsg.lib()
+    assert lib.hsg_init_lattice(None, None) == -1
+    assert lib.hsg_sweep(None, None, 1, None) == -1
+    d = _desc(hsg, spins=None)
+    assert lib.hsg_init_lattice(ctypes.byref(d), None) == -1
+    assert b"buffers" in lib.hsg_last_error()
+    d = _desc(hsg, work_bytes=16)
+    assert lib.hsg_init_lattice(ctypes.byref(d), None) == -1
+    assert b"work buffer too small" in lib.hsg_last_error()
+
+
+@pytest.mark.parametrize("T,k,n_or,R,flags,n", [
+    (0.0, 1, 0, 0, 0, 1), (-1.0, 1, 0, 0, 0, 1), (float("nan"), 1, 0, 0, 0, 1),
+    (1.0, 0, 0, 0, 0, 1), (1.0, -1, 1, 0, 0, 1), (1.0, 1, -1, 0, 0, 1),
+    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1),
+    (1.0, 70000, 0, 0, 0, 1)])
+def test_sweep_rejects_bad_params(hsg, T, k, n_or, R, flags, n):
+    lib = hsg.lib()
+    d = _desc(hsg)
+    p = hsg._SweepParams(T, k, n_or, R, flags)
+    assert lib.hsg_sweep(ctypes.byref(d), ctypes.byref(p), n, None) == -1
+    assert d.sweep == 0
+
+
+def test_sweep_counter_overflow_rejected(hsg):
+    lib = hsg.lib()
+    d = _desc(hsg, sweep=2 ** 32 - 1)
+    p = hsg._SweepParams(1.0, 1, 0, 0, 0)
+    assert lib.hsg_sweep(ctypes.byref(d), ctypes.byref(p), 2, None) == -1
+    assert b"2^32" in lib.hsg_last_error()
+
+
+def test_overlap_requires_matching_lattices(hsg):
+    lib = hsg.lib()
+    a, b = _desc(hsg), _desc(hsg, L=10, work_bytes=hsg.lattice_bytes(10)[2])
+    assert lib.hsg_overlap(ctypes.byref(a), ctypes.byref(b), ctypes.c_void_p(0x5000), None) == -1
+    assert b"same L" in lib.hsg_last_error()
+    assert lib.hsg_energy(ctypes.byref(a), 1, None, None) == -1
+
+
+def test_product_path_has_no_fallback(tmp_path, monkeypatch):
+    import importlib
+
+    import paper_1006_2566_amd as m
+    monkeypatch.setattr(m, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(m, "_lib", None)
+    with pytest.raises(ImportError):
+        m.lib()
+    importlib.reload(m)

@@ -1,0 +1,253 @@
+"""GPU parity: the HIP library, called through its C interface, against the CPU
+oracle on the same seeded inputs and the same Philox draws.
+
+Bar: binary32 spins within 1e-5 and binary64 within 1e-12 of the oracle's,
+energies within 1e-5 (binary32 data) and 1e-12 (binary64) relative.  Both sides
+spell out the same operations, so spins are expected equal bit for bit; the only
+arithmetic that differs is exp (one ulp either side), which can move a Metropolis
+decision only when the uniform lies within about 1e-7 of exp(-beta dE).  The oracle
+flags every decision within 1e-6 of its threshold, and the sites such a decision
+can reach (its causal cone, tracked by the oracle's taint map) are left out of
+the spin comparison; their number is printed and bounded.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+F32, F64 = np.float32, np.float64
+TOL = {F32: 1e-5, F64: 1e-12}
+
+
+@pytest.fixture(scope="module")
+def hsg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1006_2566_amd as m
+    m.lib()
+    return m
+
+
+def tdtype(dt):
+    return torch.float32 if dt == F32 else torch.float64
+
+
+def gpu_run(hsg, L, seed, spins, J, *, T, k=1, n_or=0, R=0, n_sweeps=1, heat_bath=False,
+            sweep0=0):
+    lat = hsg.Lattice(L, tdtype(spins.dtype), seed=seed, init=None)
+    lat.load(torch.from_numpy(spins), torch.from_numpy(J))
+    lat.sweep_index = sweep0
+    lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=n_sweeps, heat_bath=heat_bath)
+    s = lat.export()[0].cpu().numpy()
+    return s, lat.energy().item(), lat
+
+
+def oracle_run(L, seed, spins, J, *, T, k=1, n_or=0, R=0, n_sweeps=1, heat_bath=False,
+               sweep0=0):
+    s = spins.copy()
+    taint = np.zeros(L ** 3, dtype=np.uint8)
+    r = O.sweep(L, seed, s, J, T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=n_sweeps,
+                sweep0=sweep0, heat_bath=heat_bath, E=O.energy(L, spins, J), taint=taint)
+    return s, r, taint
+
+
+def compare(got, ref, taint, dtype, label, max_tainted_frac=0.01):
+    ok = taint == 0
+    n_bad = int((~ok).sum())
+    err = float(np.abs(got[:, ok].astype(F64) - ref[:, ok].astype(F64)).max()) if ok.any() else 0.0
+    same = float((got[:, ok] == ref[:, ok]).all(axis=0).mean()) if ok.any() else 1.0
+    print(f"[parity] {label}: max|d|={err:.3e} bitwise={same:.6f} tainted={n_bad}", flush=True)
+    assert err <= TOL[dtype], label
+    assert n_bad <= max(8, max_tainted_frac * taint.size), label
+
+
+# ------------------------------------------------------------ initial state
+@pytest.mark.parametrize("L", [2, 8, 24, 64])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_init_matches_oracle(hsg, L, dtype):
+    lat = hsg.Lattice(L, tdtype(dtype), seed=12345 + L)
+    s, J = (t.cpu().numpy() for t in lat.export())
+    rs, rJ = O.init(L, 12345 + L, dtype)
+    np.testing.assert_array_equal(s, rs)  # no library transcendental on this path
+    # couplings go through log(): one ulp apart at most on either side
+    np.testing.assert_allclose(J, rJ, rtol=4 * np.finfo(dtype).eps, atol=4 * np.finfo(dtype).eps)
+    E = lat.energy().item()
+    assert abs(E - O.energy(L, rs, rJ)) <= TOL[dtype] * max(1.0, abs(E))
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_import_export_roundtrip(hsg, dtype):
+    L = 10
+    s, J = inputs.random_state(L, 4, dtype)
+    lat = hsg.Lattice(L, tdtype(dtype), init=None)
+    lat.load(torch.from_numpy(s), torch.from_numpy(J))
+    s2, J2 = (t.cpu().numpy() for t in lat.export())
+    np.testing.assert_array_equal(s2, s)
+    np.testing.assert_array_equal(J2, J)
+
+
+@pytest.mark.parametrize("L", [2, 4, 8, 24, 66])
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_energy_matches_oracle(hsg, L, dtype):
+    s, J = inputs.random_state(L, 7 + L, dtype)
+    lat = hsg.Lattice(L, tdtype(dtype), init=None)
+    lat.load(torch.from_numpy(s), torch.from_numpy(J))
+    ref = O.energy(L, s, J)
+    for recompute in (False, True):
+        E = lat.energy(recompute=recompute).item()
+        assert abs(E - ref) <= 1e-12 * max(1.0, abs(ref)), (recompute, E, ref)
+
+
+# --------------------------------------------------------------- one sweep
+SWEEP_CASES = [
+    # L, dtype, T, k, n_or, R, heat_bath
+    (8, F64, 1.0, 1, 0, 0, False),        # smallest workload: L=8, binary64, 1 hit
+    (8, F32, 1.0, 1, 0, 0, False),
+    (2, F32, 1.0, 3, 1, 0, False),        # L=2: the +x and -x neighbours coincide
+    (4, F64, 0.7, 2, 1, 0, False),
+    (6, F32, math.inf, 2, 0, 0, False),   # beta = 0: every trial accepted
+    (16, F32, 0.2, 4, 1, 0, False),
+    (24, F32, 0.5, 8, 1, 0, False),       # L/2 = 12: ragged tile in x
+    (24, F64, 0.3, 4, 2, 1, False),       # renormalise after the sweep
+    (48, F32, 0.12, 4, 0, 0, False),
+    (64, F32, 0.2, 4, 1, 0, False),
+    (64, F32, 1.0, 1, 1, 0, False),
+    (64, F64, 0.5, 8, 1, 0, False),
+    (96, F32, 0.5, 1, 0, 0, False),
+    (128, F32, 0.3, 4, 2, 1, False),
+    (12, F32, 1.0, 0, 3, 0, False),       # over-relaxation only (the paper's benchmark)
+    (64, F32, 1.0, 0, 1, 0, False),
+    (16, F32, 0.5, 1, 1, 0, True),        # heat bath
+    (24, F64, 0.25, 2, 0, 0, True),
+    (32, F32, 5.0, 3, 0, 0, True),
+]
+
+
+@pytest.mark.parametrize("L,dtype,T,k,n_or,R,hb", SWEEP_CASES)
+def test_one_sweep_matches_oracle(hsg, L, dtype, T, k, n_or, R, hb):
+    seed = 1000 + L + k
+    s, J = inputs.random_state(L, 2 * L + k, dtype)
+    got, E_gpu, _ = gpu_run(hsg, L, seed, s, J, T=T, k=k, n_or=n_or, R=R, heat_bath=hb, sweep0=5)
+    ref, r, taint = oracle_run(L, seed, s, J, T=T, k=k, n_or=n_or, R=R, heat_bath=hb, sweep0=5)
+    compare(got, ref, taint, dtype, f"L={L} {np.dtype(dtype).name} T={T} k={k} n_or={n_or} "
+            f"R={R} hb={hb} flagged={r['n_flagged']}")
+    if not taint.any():
+        assert abs(E_gpu - r["E"]) <= TOL[dtype] * max(1.0, abs(r["E"]))
+
+
+@pytest.mark.parametrize("k", [1, 4, 8])
+def test_full_size_sweep_matches_oracle(hsg, k):
+    """L = 256 (16.8M spins), binary32, the launch configuration the benchmark
+    times (hsg_sweep's colour passes): one sweep of k hits + 1 over-relaxation phase
+    from a seeded state, every site compared."""
+    L, seed = 256, 1
+    s, J = inputs.random_state(L, 256, F32)
+    got, E_gpu, _ = gpu_run(hsg, L, seed, s, J, T=0.3, k=k, n_or=1)
+    ref, r, taint = oracle_run(L, seed, s, J, T=0.3, k=k, n_or=1)
+    compare(got, ref, taint, F32, f"L=256 k={k} flagged={r['n_flagged']}", 0.001)
+    assert abs(E_gpu - r["E"]) <= 1e-5 * abs(r["E"])
+
+
+def test_config1_trajectory_matches_golden(hsg):
+    """Smallest workload (L=8, binary64, T=1, k=1, seed 1, Philox initial state):
+    every one of the 10 sweeps against the stored oracle run."""
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "config1_L8_f64.json")) as f:
+        ref = json.load(f)
+    lat = hsg.Lattice(8, torch.float64, seed=1)
+    assert abs(lat.energy().item() - ref["E0"]) <= 1e-12 * abs(ref["E0"])
+    for n, rec in enumerate(ref["sweeps"]):
+        lat.sweep(T=1.0, k=1, n_sweeps=1)
+        E_t = lat.energy().item()
+        E_r = lat.energy(recompute=True).item()
+        assert abs(E_t - rec["E_tracked"]) <= 1e-12 * abs(rec["E_tracked"]), n
+        assert abs(E_r - rec["E_recomputed"]) <= 1e-12 * abs(rec["E_recomputed"]), n
+    s = lat.export()[0].cpu().numpy()
+    err = np.abs(s - np.array(ref["final_spins"])).max()
+    print(f"[parity] config1 10 sweeps: max|d|={err:.3e}", flush=True)
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_multi_sweep_trajectory(hsg, dtype):
+    L, seed = 16, 77
+    s, J = inputs.random_state(L, 3, dtype)
+    got, E_gpu, _ = gpu_run(hsg, L, seed, s, J, T=0.6, k=4, n_or=1, R=10, n_sweeps=20)
+    ref, r, taint = oracle_run(L, seed, s, J, T=0.6, k=4, n_or=1, R=10, n_sweeps=20)
+    compare(got, ref, taint, dtype, f"L=16 20 sweeps flagged={r['n_flagged']}", 0.5)
+    if not taint.any():
+        assert abs(E_gpu - r["E"]) <= TOL[dtype] * abs(r["E"])
+
+
+def test_split_calls_equal_single_call(hsg):
+    L = 24
+    a = hsg.Lattice(L, torch.float32, seed=9)
+    b = hsg.Lattice(L, torch.float32, seed=9)
+    a.sweep(T=0.4, k=4, n_or=1, renorm_every=3, n_sweeps=7)
+    for _ in range(7):
+        b.sweep(T=0.4, k=4, n_or=1, renorm_every=3, n_sweeps=1)
+    assert a.sweep_index == b.sweep_index == 7
+    assert torch.equal(a.spins, b.spins)
+    assert abs(a.energy().item() - b.energy().item()) <= 1e-12 * abs(a.energy().item())
+
+
+# ---------------------------------------------------------------- overlap
+@pytest.mark.parametrize("dtype", [F32, F64])
+def test_overlap_matches_oracle(hsg, dtype):
+    L = 20
+    sa, J = inputs.random_state(L, 1, dtype)
+    sb, _ = inputs.random_state(L, 2, dtype)
+    a = hsg.Lattice(L, tdtype(dtype), init=None)
+    b = hsg.Lattice(L, tdtype(dtype), init=None)
+    a.load(torch.from_numpy(sa), torch.from_numpy(J))
+    b.load(torch.from_numpy(sb), torch.from_numpy(J))
+    got = a.overlap(b).cpu().numpy()
+    Q, ma, mb = O.overlap(L, sa, sb)
+    # binary64 sums of N = 8000 terms in two different orders
+    np.testing.assert_allclose(got[:9], Q.ravel(), rtol=0, atol=1e-13)
+    np.testing.assert_allclose(got[9:12], ma, rtol=0, atol=1e-13)
+    np.testing.assert_allclose(got[12:15], mb, rtol=0, atol=1e-13)
+
+
+# ------------------------------------------------------ invariants on the GPU
+def test_renormalised_spins_are_unit(hsg):
+    lat = hsg.Lattice(32, torch.float32, seed=5)
+    lat.sweep(T=0.5, k=2, n_or=2, renorm_every=10, n_sweeps=30)
+    s = lat.export()[0].double()
+    assert (s.norm(dim=0) - 1).abs().max().item() <= 1e-6
+
+
+def test_over_relaxation_conserves_energy(hsg):
+    lat = hsg.Lattice(48, torch.float32, seed=6)
+    E0 = lat.energy(recompute=True).item()
+    s0 = lat.spins.clone()
+    lat.sweep(T=1.0, k=0, n_or=1, n_sweeps=20)
+    E1 = lat.energy(recompute=True).item()
+    assert abs(E1 - E0) <= 1e-5 * abs(E0)
+    assert (lat.spins - s0).abs().max().item() > 0.1
+
+
+@pytest.mark.parametrize("dtype,tol", [(torch.float32, 1e-5), (torch.float64, 1e-12)])
+def test_tracked_energy_equals_recomputed(hsg, dtype, tol):
+    lat = hsg.Lattice(32, dtype, seed=8)
+    lat.sweep(T=0.3, k=4, n_or=1, renorm_every=10, n_sweeps=50)
+    Et, Er = lat.energy().item(), lat.energy(recompute=True).item()
+    assert abs(Et - Er) <= tol * abs(Er), (Et, Er)
+
+
+def test_infinite_temperature_uniform(hsg):
+    from scipy import stats
+    lat = hsg.Lattice(32, torch.float32, seed=10)
+    lat.sweep(T=math.inf, k=1, n_sweeps=3)
+    s = lat.export()[0].cpu().numpy()
+    for a in range(3):
+        assert stats.kstest(s[a], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
