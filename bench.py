@@ -39,18 +39,24 @@ def parse():
     ap.add_argument("--renorm-every", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--flags", type=int, default=None,
+                    help="hsg_sweep flags for the timed sweeps (default: the library's choice)")
+    ap.add_argument("--counters", action="store_true",
+                    help="short run for hardware-counter collection: one 1 GiB device copy "
+                         "(calibrates FETCH_SIZE / WRITE_SIZE), then 2 sweeps of the headline "
+                         "configuration; prints no JSON")
     return ap.parse_args()
 
 
-def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup):
+def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup, flags=0):
     """Average ms per sweep over `steps` sweeps, HIP events on the launch stream."""
-    lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=warmup)
+    lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=warmup, flags=flags)
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     t0.record(stream)
-    lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=steps)
+    lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=steps, flags=flags)
     t1.record(stream)
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
@@ -96,13 +102,23 @@ def main():
 
     L, R = args.L, args.renorm_every
     N = L ** 3
+    flags = hsg.DEFAULT_SWEEP_FLAGS if args.flags is None else args.flags
     lat = hsg.Lattice(L, torch.float32, seed=1)
+    if args.counters:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # 1 GiB read + 1 GiB written
+        torch.cuda.synchronize()
+        lat.sweep(T=args.T, k=args.k, n_or=args.n_or, renorm_every=R, n_sweeps=2, flags=flags)
+        torch.cuda.synchronize()
+        return
 
     per_k = {}
     ks = [args.k] + [int(x) for x in args.also_k.split(",") if x.strip()]
     for k in ks:
         ms = time_sweeps(lat, torch, T=args.T, k=k, n_or=args.n_or, R=R, steps=args.steps,
-                         warmup=args.warmup)
+                         warmup=args.warmup, flags=flags)
         upd = N * (k + args.n_or) / (ms * 1e6)
         per_k[str(k)] = {"ms_per_step": ms, "spin_updates_per_ns": upd,
                          "site_sweeps_per_ns": N / (ms * 1e6),
@@ -112,7 +128,7 @@ def main():
     # dominant kernel: the Metropolis colour pass.  Average duration of one such pass,
     # timed alone (k hits, no over-relaxation) with events on the launch stream.
     ms_mh_sweep = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=args.steps,
-                              warmup=2)
+                              warmup=2, flags=flags)
     ms_pass = ms_mh_sweep / 2.0
     head = per_k[str(args.k)]
     bytes_pass = N / 2 * BYTES_PER_SITE_PHASE * 2 / 2  # 36 B per site-phase, half the sites
@@ -130,7 +146,7 @@ def main():
            "config": {"workload": f"single lattice L={L} binary32, Gaussian couplings, "
                                   f"T={args.T}, sweep = Metropolis k={args.k} + "
                                   f"{args.n_or} over-relaxation, renormalise every {R}",
-                      "L": L, "k": args.k, "n_or": args.n_or, "T": args.T},
+                      "L": L, "k": args.k, "n_or": args.n_or, "T": args.T, "flags": flags},
            "per_k": per_k, "roofline": roofline}
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args)

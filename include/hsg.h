@@ -14,7 +14,7 @@
  * then n_or over-relaxation phases (reflection of sigma about h, §4), each phase
  * being the colour-0 pass followed by the colour-1 pass.  Random numbers, which the
  * paper leaves aside, come from Philox4x32-10 keyed by the lattice seed with counter
- * (site, sweep, (phase << 16) | hit, stream tag).
+ * (sweep, site, (phase << 16) | hit, stream tag).
  *
  * Conventions for every function:
  *  - Return HSG_OK (0) or a negative HSG_E* code; never abort, never throw.  After an
@@ -52,8 +52,11 @@ extern "C" {
 
 #define HSG_L_MAX 1290 /* largest L: N = L^3 < 2^31 keeps every site index in 32 bits */
 
-/* Sweep flags (hsg_sweep_params.flags). */
-#define HSG_HEAT_BATH 1 /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
+/* Sweep flags (hsg_sweep_params.flags).  The last two change only the order in which
+ * memory is touched, never a result. */
+#define HSG_HEAT_BATH 1    /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
+#define HSG_SNAKE 2        /* successive colour passes walk the lattice in opposite z order */
+#define HSG_STREAM_SPINS 4 /* spin loads/stores carry the non-temporal hint */
 
 typedef struct hsg_lattice {
   int32_t L;         /* even, 2 <= L <= HSG_L_MAX */
@@ -73,7 +76,7 @@ typedef struct hsg_sweep_params {
   int32_t n_or;         /* over-relaxation phases per sweep, >= 0; k_hits + n_or >= 1 */
   int32_t renorm_every; /* R > 0: after sweep s with (s+1) % R == 0 every spin is
                            divided by its length; 0 = never */
-  int32_t flags;        /* 0 or HSG_HEAT_BATH */
+  int32_t flags;        /* OR of HSG_HEAT_BATH, HSG_SNAKE, HSG_STREAM_SPINS */
 } hsg_sweep_params;
 
 /* Sizes of the three device buffers of an L^3 lattice of the given dtype.  Any
@@ -84,7 +87,7 @@ int hsg_lattice_bytes(int32_t L, int32_t dtype, size_t *spin_bytes, size_t *J_by
 
 /* Random initial state from lat->seed (§2 model): spins uniform on the sphere,
  * couplings N(0,1) by Box-Muller, both from Philox (stream tags 1 and 2, counter
- * word 0 = canonical site index); then *lat->E = H and the scratch is cleared.
+ * (0, canonical site index, 0, tag)); then *lat->E = H and the scratch is cleared.
  * lat->sweep is left as it is. */
 int hsg_init_lattice(hsg_lattice *lat, void *stream);
 

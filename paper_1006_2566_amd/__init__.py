@@ -25,6 +25,10 @@ LIB_PATH = os.path.join(_HERE, "libhsg.so")
 
 HSG_F32, HSG_F64 = 0, 1
 HSG_HEAT_BATH = 1
+HSG_SNAKE = 2
+HSG_STREAM_SPINS = 4
+# traversal flags the benchmark uses unless told otherwise (order only; results unchanged)
+DEFAULT_SWEEP_FLAGS = HSG_SNAKE
 L_MAX = 1290
 
 
@@ -168,9 +172,9 @@ class Lattice:
 
     # --------------------------------------------------------------- dynamics
     def sweep(self, T: float, k: int = 1, n_or: int = 0, renorm_every: int = 0,
-              n_sweeps: int = 1, heat_bath: bool = False, stream=None) -> None:
+              n_sweeps: int = 1, heat_bath: bool = False, flags: int = 0, stream=None) -> None:
         p = _SweepParams(float(T), int(k), int(n_or), int(renorm_every),
-                         HSG_HEAT_BATH if heat_bath else 0)
+                         (HSG_HEAT_BATH if heat_bath else 0) | int(flags))
         check(lib().hsg_sweep(ctypes.byref(self._d), ctypes.byref(p), int(n_sweeps),
                               _stream(stream)))
 

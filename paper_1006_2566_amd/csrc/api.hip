@@ -62,6 +62,8 @@ int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hi
   a.k_hits = p->k_hits;
   a.g = g;
   const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
+  const bool snake = (p->flags & HSG_SNAKE) != 0, nt = (p->flags & HSG_STREAM_SPINS) != 0;
+  int32_t pass_count = 0;
   for (int32_t n = 0; n < n_sweeps; ++n) {
     const uint64_t sweep = lat->sweep + (uint64_t)n;
     a.sweep = (uint32_t)sweep;
@@ -70,8 +72,10 @@ int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hi
       a.phase = (uint32_t)phase;
       for (int32_t colour = 0; colour < 2; ++colour) {
         a.colour = colour;
+        a.reverse = snake ? (pass_count & 1) : 0;
+        ++pass_count;
         int rc = device_status(
-            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, a, st), "colour pass");
+            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, nt, a, st), "colour pass");
         if (rc) return rc;
       }
     }
@@ -170,7 +174,8 @@ int hsg_sweep(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, voi
   if (p->n_or > 0x7FFF || p->k_hits > 0xFFFF)
     return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
   if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
-  if (p->flags & ~HSG_HEAT_BATH) return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
+  if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE | HSG_STREAM_SPINS))
+    return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
   if (n_sweeps < 0) return fail(HSG_EINVAL, "n_sweeps must be >= 0");
   if (lat->sweep + (uint64_t)n_sweeps > 0x100000000ull)
     return fail(HSG_EINVAL, "sweep index would pass 2^32");

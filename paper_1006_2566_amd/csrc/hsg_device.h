@@ -22,8 +22,9 @@ struct Word4 {
 // Philox4x32-10 (Salmon et al., SC'11).  Each round takes two 32x32->64 products
 // of counter words 0 and 2 with the round multipliers and mixes their halves with
 // words 1 and 3 and the key; the key advances by the Weyl constants between rounds.
-// A product of a wave-uniform word stays on the scalar unit, so with a uniform key
-// and uniform counter words 1..3 the first two rounds cost one vector product each.
+// Callers put the only per-lane word (the site) in word 1 and wave-uniform values in
+// words 0, 2, 3 and the key: the products of the first rounds then stay on the
+// scalar unit (16 vector products per block instead of 18).
 __device__ __forceinline__ Word4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
@@ -45,9 +46,12 @@ __device__ __forceinline__ Word4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
 // Uniform in (0,1): the top 23 bits of w as an odd multiple of 2^-24.  Exact in
 // binary32 and binary64 (the same value in both precisions).
 template <typename R>
+__device__ __forceinline__ R odd_part(uint32_t w) {
+  return (R)(((w >> 9) << 1) | 1u);  // < 2^24, exactly representable
+}
+template <typename R>
 __device__ __forceinline__ R unit_uniform(uint32_t w) {
-  const uint32_t odd = ((w >> 9) << 1) | 1u;  // < 2^24, exactly representable
-  return (R)odd * (R)0x1p-24;
+  return odd_part<R>(w) * (R)0x1p-24;
 }
 
 template <typename R>
@@ -119,12 +123,29 @@ __device__ __forceinline__ double dev_expm1(double a) { return expm1(a); }
 __device__ __forceinline__ float dev_rint(float a) { return rintf(a); }
 __device__ __forceinline__ double dev_rint(double a) { return rint(a); }
 
+// Metropolis acceptance exp(x) for x = -beta dE.  Binary32 uses the hardware 2^y
+// (v_exp_f32, within 1 ulp) at y = x log2(e): the result is within 2e-8 of exp(x)
+// everywhere it can matter (y*2^y is at most 0.53 times the 4e-8 rounding of y), far
+// inside the 1e-6 band in which decisions are flagged as too close to call.
+__device__ __forceinline__ float accept_prob(float x) {
+  return __builtin_amdgcn_exp2f(x * 0x1.715476p+0f);
+}
+__device__ __forceinline__ double accept_prob(double x) { return exp(x); }
+
 // (sin, cos) of 2 pi u for an exact uniform u.  t = 4u splits exactly into its
 // nearest integer q (t is never a half-integer) and r = t - q, 2 pi u = (pi/2)(q + r);
 // the quadrant q mod 4 rotates (sin, cos) of (pi/2) r.
 template <typename R>
+__device__ __forceinline__ void sincos_2pi_t(R t, R& s_out, R& c_out);
+
+template <typename R>
 __device__ __forceinline__ void sincos_2pi(R u, R& s_out, R& c_out) {
-  const R t = u * (R)4;
+  sincos_2pi_t(u * (R)4, s_out, c_out);
+}
+
+// Same, given t = 4u.
+template <typename R>
+__device__ __forceinline__ void sincos_2pi_t(R t, R& s_out, R& c_out) {
   const R q = dev_rint(t);
   const R r = t - q;
   R s, c;
@@ -158,10 +179,39 @@ __device__ __forceinline__ Vec3<R> sphere_point(R u0, R u1) {
   return Vec3<R>{rho * c, rho * s, z};
 }
 
+// The same point straight from two Philox words: with u = odd * 2^-24 exact, both
+// 2u - 1 = odd * 2^-23 - 1 and 4u = odd * 2^-22 are exact, so folding the scale
+// into one operation gives identical bits.
+// Correctly rounded square root of a positive normal binary32 x: the hardware root
+// (within 1 ulp) is moved to its neighbour when the residual x - r*r of the neighbour
+// shows that neighbour is the nearer root.  sqrtf performs the same steps plus
+// scaling for denormal and special inputs, which the sphere point never produces
+// (there 1 - z^2 >= 2^-22).
+__device__ __forceinline__ float sqrt_rn_normal(float x) {
+  const float r = __builtin_amdgcn_sqrtf(x);
+  const float down = __uint_as_float(__float_as_uint(r) - 1u);
+  const float up = __uint_as_float(__float_as_uint(r) + 1u);
+  float out = fmaf(-down, r, x) <= 0.0f ? down : r;
+  out = fmaf(-up, r, x) > 0.0f ? up : out;
+  return out;
+}
+__device__ __forceinline__ double sqrt_rn_normal(double x) { return sqrt(x); }
+
+template <typename R>
+__device__ __forceinline__ Vec3<R> sphere_point_words(uint32_t w0, uint32_t w1) {
+  const R z = dev_fma(odd_part<R>(w0), (R)0x1p-23, (R)-1);
+  const R rho = sqrt_rn_normal(dev_fma(-z, z, (R)1));
+  R s, c;
+  sincos_2pi_t(odd_part<R>(w1) * (R)0x1p-22, s, c);
+  return Vec3<R>{rho * c, rho * s, z};
+}
+
 // Exact draw from the conditional law exp(beta sigma.h) on the sphere.  With
-// a = beta |h|, the cosine to the field is c = 1 + log1p(-(1-u0)(1-e^{-2a}))/a
-// (c = 2 u0 - 1 for a = 0), the azimuth is 2 pi u1, and the tangent frame about
-// n = h/|h| is the branch-free orthonormal basis of Duff et al. (JCGT 2017).
+// a = beta |h|, w = 1 - u0 and q = 1 - e^{-2a}, the cosine to the field is
+// c = 1 + log(1 - w q)/a, evaluated as log1p(-w q) while w q <= 1/2 and as
+// log(u0 + w e^{-2a}) (one fused multiply-add, no cancellation) above; c = 2 u0 - 1
+// for a = 0.  The azimuth is 2 pi u1, and the tangent frame about n = h/|h| is the
+// branch-free orthonormal basis of Duff et al. (JCGT 2017).
 template <typename R>
 __device__ __forceinline__ Vec3<R> heat_bath_point(const Vec3<R>& h, R beta, R u0, R u1) {
   const R hh = dot3(h, h);
@@ -169,8 +219,10 @@ __device__ __forceinline__ Vec3<R> heat_bath_point(const Vec3<R>& h, R beta, R u
   const R a = beta * hn;
   R c;
   if (a > (R)0) {
-    const R one_m_u = (R)1 - u0;
-    c = (R)1 + dev_div(dev_log1p(-(one_m_u * -dev_expm1((R)-2 * a))), a);
+    const R w = (R)1 - u0;
+    const R wq = w * -dev_expm1((R)-2 * a);
+    const R lg = wq <= (R)0.5 ? dev_log1p(-wq) : dev_log(dev_fma(w, dev_exp((R)-2 * a), u0));
+    c = (R)1 + dev_div(lg, a);
   } else {
     c = (R)2 * u0 - (R)1;
   }

@@ -62,11 +62,13 @@ struct PassArgs {
   uint32_t phase;
   int32_t k_hits;
   int32_t colour;
+  int32_t reverse;  // walk the tiles from the last z plane to the first
   Geometry g;
 };
 
 template <typename R>
-hipError_t launch_colour_pass(PassMode mode, const PassArgs<R>& a, hipStream_t stream);
+hipError_t launch_colour_pass(PassMode mode, bool stream_spins, const PassArgs<R>& a,
+                              hipStream_t stream);
 
 // *E += sum of the n partials (fixed order); the partials are then zeroed.
 hipError_t launch_fold_partials(double* partials, int32_t n, double* E, hipStream_t stream);

@@ -43,14 +43,14 @@ __global__ __launch_bounds__(256) void init_kernel(int32_t L, uint32_t k0, uint3
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N;
        e += (int64_t)gridDim.x * blockDim.x) {
     const SiteOf st = site_of(e, L);
-    const Word4 ws = philox10(st.canon, 0u, 0u, kTagInitSpin, k0, k1);
+    const Word4 ws = philox10(0u, st.canon, 0u, kTagInitSpin, k0, k1);
     const Vec3<R> s = sphere_point(unit_uniform<R>(ws.w0), unit_uniform<R>(ws.w1));
     const int64_t base = (int64_t)3 * st.c * Nh + st.ic;
     spins[base] = s.x;
     spins[base + Nh] = s.y;
     spins[base + 2 * Nh] = s.z;
     // Box-Muller: (u0,u1) -> Jx, Jy; (u2,u3) -> Jz
-    const Word4 wj = philox10(st.canon, 0u, 0u, kTagInitJ, k0, k1);
+    const Word4 wj = philox10(0u, st.canon, 0u, kTagInitJ, k0, k1);
     R sn, cs;
     const R r01 = dev_sqrt((R)-2 * dev_log(unit_uniform<R>(wj.w0)));
     sincos_2pi(unit_uniform<R>(wj.w1), sn, cs);

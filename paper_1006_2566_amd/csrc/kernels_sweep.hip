@@ -51,10 +51,24 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
   return xcd * q + min(xcd, r) + local;
 }
 
-template <typename R, PassMode MODE>
+// Spin accesses, optionally with the non-temporal hint (streamed past the caches so
+// that the couplings, reused by every pass, keep their place).
+template <bool NT, typename R>
+__device__ __forceinline__ R load_spin(const R* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT, typename R>
+__device__ __forceinline__ void store_spin(R v, R* p) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <typename R, PassMode MODE, bool NT>
 __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
   const Geometry& g = a.g;
-  const int32_t tile = xcd_tile((int32_t)blockIdx.x, g.n_blocks);
+  int32_t tile = xcd_tile((int32_t)blockIdx.x, g.n_blocks);
+  if (a.reverse) tile = g.n_blocks - 1 - tile;
   const int32_t tx = tile % g.tiles_x;
   const int32_t rest = tile / g.tiles_x;
   const int32_t ty = rest % g.tiles_y;
@@ -88,16 +102,17 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const R* sn = a.spins.p[nc + k];
-      R acc = j_px * sn[n_px];
-      acc = dev_fma(j_mx, sn[n_mx], acc);
-      acc = dev_fma(j_py, sn[n_py], acc);
-      acc = dev_fma(j_my, sn[n_my], acc);
-      acc = dev_fma(j_pz, sn[n_pz], acc);
-      acc = dev_fma(j_mz, sn[n_mz], acc);
+      R acc = j_px * load_spin<NT>(sn + n_px);
+      acc = dev_fma(j_mx, load_spin<NT>(sn + n_mx), acc);
+      acc = dev_fma(j_py, load_spin<NT>(sn + n_py), acc);
+      acc = dev_fma(j_my, load_spin<NT>(sn + n_my), acc);
+      acc = dev_fma(j_pz, load_spin<NT>(sn + n_pz), acc);
+      acc = dev_fma(j_mz, load_spin<NT>(sn + n_mz), acc);
       hc[k] = acc;
     }
     const Vec3<R> h{hc[0], hc[1], hc[2]};
-    Vec3<R> s{a.spins.p[oc + 0][own], a.spins.p[oc + 1][own], a.spins.p[oc + 2][own]};
+    Vec3<R> s{load_spin<NT>(a.spins.p[oc + 0] + own), load_spin<NT>(a.spins.p[oc + 1] + own),
+              load_spin<NT>(a.spins.p[oc + 2] + own)};
 
     if constexpr (MODE == PassMode::OverRelax) {
       s = reflect(s, h);
@@ -106,21 +121,20 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
       const uint32_t tag = MODE == PassMode::Metropolis ? kTagMetropolis : kTagHeatBath;
       R sh = dot3(s, h);
       for (int32_t j = 0; j < a.k_hits; ++j) {
-        const Word4 w = philox10(site, a.sweep, (a.phase << 16) | (uint32_t)j, tag, a.seed_lo,
+        const Word4 w = philox10(a.sweep, site, (a.phase << 16) | (uint32_t)j, tag, a.seed_lo,
                                  a.seed_hi);
-        const R u0 = unit_uniform<R>(w.w0), u1 = unit_uniform<R>(w.w1);
         Vec3<R> trial;
         if constexpr (MODE == PassMode::Metropolis) {
-          trial = sphere_point(u0, u1);
+          trial = sphere_point_words<R>(w.w0, w.w1);
         } else {
-          trial = heat_bath_point(h, a.beta, u0, u1);
+          trial = heat_bath_point(h, a.beta, unit_uniform<R>(w.w0), unit_uniform<R>(w.w1));
         }
         const R th = dot3(trial, h);
         const R dE = sh - th;
         bool accept = true;
         if constexpr (MODE == PassMode::Metropolis) {
           const R u2 = unit_uniform<R>(w.w2);
-          accept = (dE <= (R)0) || (u2 < dev_exp(-a.beta * dE));
+          accept = (dE <= (R)0) || (u2 < accept_prob(-a.beta * dE));
         }
         if (accept) {
           s = trial;
@@ -129,9 +143,9 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
         }
       }
     }
-    a.spins.p[oc + 0][own] = s.x;
-    a.spins.p[oc + 1][own] = s.y;
-    a.spins.p[oc + 2][own] = s.z;
+    store_spin<NT>(s.x, a.spins.p[oc + 0] + own);
+    store_spin<NT>(s.y, a.spins.p[oc + 1] + own);
+    store_spin<NT>(s.z, a.spins.p[oc + 2] + own);
   }
 
   if constexpr (MODE != PassMode::OverRelax) {
@@ -143,25 +157,38 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
   }
 }
 
-template <typename R>
-hipError_t launch_colour_pass(PassMode mode, const PassArgs<R>& a, hipStream_t stream) {
+template <typename R, bool NT>
+static void launch_mode(PassMode mode, const PassArgs<R>& a, hipStream_t stream) {
   const dim3 grid((unsigned)a.g.n_blocks), block(256);
   switch (mode) {
     case PassMode::Metropolis:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis>), grid, block, 0, stream, a);
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis, NT>), grid, block, 0, stream,
+                         a);
       break;
     case PassMode::OverRelax:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::OverRelax>), grid, block, 0, stream, a);
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::OverRelax, NT>), grid, block, 0, stream,
+                         a);
       break;
     case PassMode::HeatBath:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::HeatBath>), grid, block, 0, stream, a);
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::HeatBath, NT>), grid, block, 0, stream,
+                         a);
       break;
   }
+}
+
+template <typename R>
+hipError_t launch_colour_pass(PassMode mode, bool stream_spins, const PassArgs<R>& a,
+                              hipStream_t stream) {
+  if (stream_spins)
+    launch_mode<R, true>(mode, a, stream);
+  else
+    launch_mode<R, false>(mode, a, stream);
   return hipGetLastError();
 }
 
-template hipError_t launch_colour_pass<float>(PassMode, const PassArgs<float>&, hipStream_t);
-template hipError_t launch_colour_pass<double>(PassMode, const PassArgs<double>&, hipStream_t);
+template hipError_t launch_colour_pass<float>(PassMode, bool, const PassArgs<float>&, hipStream_t);
+template hipError_t launch_colour_pass<double>(PassMode, bool, const PassArgs<double>&,
+                                                hipStream_t);
 
 // *E += sum of the partials in a fixed order (strided per thread, then a fixed tree),
 // and the partials are reset to zero for the next sweeps.

@@ -286,7 +286,7 @@ def test_k_hits_equal_field_fixed_repeats():
     for i in np.where(c == 0)[0]:
         sig = s0[:, i].copy()
         for j in range(3):
-            w = O.philox([[i, 0, j, O.TAG_MH]], 99)[0]
+            w = O.philox([[0, i, j, O.TAG_MH]], 99)[0]
             u = O.u01(w)
             t = O.trial_spin(u[0], u[1], F64)
             dE = float(sig @ h) - float(t @ h)
