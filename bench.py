@@ -41,6 +41,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--flags", type=int, default=None,
                     help="hsg_sweep flags for the timed sweeps (default: the library's choice)")
+    ap.add_argument("--batch-cycles", type=int, default=2,
+                    help="timed cycles (100 sweeps each) of the batched tempering workload; "
+                         "0 skips that leg")
+    ap.add_argument("--batch-threads", type=int, default=256)
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
                          "(calibrates FETCH_SIZE / WRITE_SIZE), then 2 sweeps of the headline "
@@ -60,6 +64,63 @@ def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup, flags=0):
     t1.record(stream)
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def batched_leg(args, torch):
+    """Parallel-tempering workload: 256 disorder samples, L uniform in {16,24,32,48},
+    2 replicas x 24 geometric temperatures in [0.12, 0.5], binary32, Metropolis k=4,
+    an exchange round every 10 sweeps and the binary64 overlap of the two replicas in
+    every slot every 100 sweeps, all in one captured graph per 100 sweeps.  Compared
+    with the same kind of lattices advanced by plain per-lattice hsg_sweep calls."""
+    import numpy as np
+
+    import paper_1006_2566_amd as hsg
+    from paper_1006_2566_amd import batch as B
+
+    specs, ladders, betas, pairs = B.pt_workload()
+    b = B.Batch(specs, threads=args.batch_threads)
+    pt = B.Tempering(b, ladders, betas, seed=1)
+    runner = B.PTRunner(b, pt, pairs, sweeps_per_exchange=10, exchanges_per_measure=10)
+    runner.run_cycle()  # eager first cycle, then the graph is captured
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(args.batch_cycles):
+        runner.run_cycle()
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    sites = float(sum(sp.L ** 3 for sp in specs))
+    sweeps = args.batch_cycles * runner.sweeps_per_cycle
+    upd = sites * 4 * sweeps / (ms * 1e6)
+    # the same lattices through plain per-lattice launches: one sample of each L,
+    # all 48 chains, 2 sweeps each, one lattice at a time, no graph
+    Ls = sorted({sp.L for sp in specs})
+    lats = []
+    for L in Ls:
+        for c in range(48):
+            lats.append(hsg.Lattice(L, torch.float32, seed=7 + 131 * c + L))
+    for lat in lats:
+        lat.sweep(T=0.3, k=4, n_sweeps=1)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for lat in lats:
+        lat.sweep(T=0.3, k=4, n_sweeps=2)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_plain = t0.elapsed_time(t1)
+    upd_plain = sum(l.N for l in lats) * 4 * 2 / (ms_plain * 1e6)
+    acc = pt.accepted.sum().item() / max(1, int(pt.round.item())) / pt.n_ladders
+    return {"workload": "256 samples x 2 replicas x 24 temperatures (12288 chains, "
+                        f"{sites:.3g} spins), L in {{16,24,32,48}}, binary32, k=4, exchange "
+                        "every 10 sweeps, overlap every 100, one graph per 100 sweeps",
+            "sweeps": sweeps, "ms": ms, "ms_per_sweep": ms / sweeps,
+            "spin_updates_per_ns": upd,
+            "plain_per_lattice_updates_per_ns": upd_plain,
+            "speedup_vs_plain": upd / upd_plain,
+            "exchange_acceptance_per_pair_round": acc,
+            "threads": args.batch_threads}
 
 
 def cpu_baseline(args):
@@ -148,6 +209,10 @@ def main():
                                   f"{args.n_or} over-relaxation, renormalise every {R}",
                       "L": L, "k": args.k, "n_or": args.n_or, "T": args.T, "flags": flags},
            "per_k": per_k, "roofline": roofline}
+    if args.batch_cycles > 0:
+        del lat
+        torch.cuda.empty_cache()
+        rec["batched"] = batched_leg(args, torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(rec), flush=True)

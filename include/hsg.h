@@ -119,6 +119,108 @@ int hsg_energy(const hsg_lattice *lat, int32_t recompute, double *out_dev, void 
  * out_dev is device memory for 15 doubles.  a's work buffer is used as scratch. */
 int hsg_overlap(const hsg_lattice *a, const hsg_lattice *b, double *out_dev, void *stream);
 
+/* ======================================================================================
+ * Batched form: many independent lattices ("chains") -- disorder samples, replicas and
+ * temperatures -- advanced by one persistent launch.  Each workgroup takes whole chains
+ * from a device work queue and runs their sweeps with workgroup barriers between colour
+ * passes; a chain computes exactly what hsg_sweep computes for the same lattice.
+ * ==================================================================================== */
+
+#define HSG_BATCH_L_MAX 256 /* largest L of a chain in a batch */
+#define HSG_CHAIN_INIT_J 8  /* chain flag: hsg_batch_init draws this chain's couplings */
+
+typedef struct hsg_chain {
+  int64_t spin_offset; /* element offset of the chain's spins (3*L^3 elements, internal
+                          layout) in hsg_batch.spins */
+  int64_t J_offset;    /* element offset of its couplings in hsg_batch.J (chains of one
+                          disorder sample share them) */
+  uint64_t seed;       /* Philox key of the chain's initial spins and Monte Carlo stream */
+  uint64_t J_seed;     /* Philox key of the couplings (read with HSG_CHAIN_INIT_J) */
+  int32_t L;           /* even, 2 <= L <= HSG_BATCH_L_MAX */
+  int32_t k_hits;      /* as hsg_sweep_params */
+  int32_t n_or;
+  int32_t renorm_every;
+  int32_t flags;       /* HSG_HEAT_BATH, HSG_CHAIN_INIT_J */
+  int32_t reserved;    /* 0 */
+} hsg_chain;           /* 56 bytes */
+
+typedef struct hsg_batch {
+  int32_t n_chains;
+  int32_t dtype;           /* HSG_F32 or HSG_F64, for every chain */
+  const hsg_chain *chains; /* device [n_chains] */
+  void *spins;             /* device: base of all chains' spins */
+  void *J;                 /* device: base of all couplings */
+  double *beta;            /* device [n_chains]: inverse temperature of each chain */
+  double *E;               /* device [n_chains]: tracked energy of each chain */
+  uint32_t *sweep;         /* device [n_chains]: next sweep index of each chain */
+  int32_t *remaining;      /* device [n_chains] or NULL: sweeps each chain still has to run;
+                              a launch runs min(n_sweeps, remaining) and subtracts them */
+  const int32_t *order;    /* device [n_chains]: a permutation, the order in which
+                              workgroups take the chains (largest L first balances load) */
+  void *work;              /* device scratch of at least hsg_batch_work_bytes bytes */
+  size_t work_bytes;
+  int32_t threads;         /* threads per workgroup: a multiple of 64 up to 1024 (0 = 256) */
+  int32_t max_groups;      /* workgroups of the persistent grid (0 = 8 per compute unit) */
+} hsg_batch;
+
+/* Scratch bytes a batch of n_chains needs (queue counters). */
+int hsg_batch_work_bytes(int32_t n_chains, size_t *work_bytes);
+
+/* Host-side check of a chain table before it is copied to the device: every chain
+ * has an even 2 <= L <= HSG_BATCH_L_MAX, k_hits/n_or/renorm_every/flags as
+ * hsg_sweep accepts them, and its spins (3*L^3 elements from spin_offset) and
+ * couplings (from J_offset) inside buffers of spin_elems and J_elems elements; the
+ * spin ranges of different chains do not overlap.  HSG_EINVAL names the first bad
+ * chain.  The device entry points trust the table, so callers run this first. */
+int hsg_batch_check(const hsg_chain *host_chains, int32_t n_chains, int64_t spin_elems,
+                    int64_t J_elems);
+
+/* Every chain: spins from its seed (as hsg_init_lattice); chains flagged
+ * HSG_CHAIN_INIT_J also draw the couplings at their J_offset from J_seed (flag exactly
+ * one chain per coupling block).  Then E = H for every chain and the work queue is
+ * cleared.  beta, sweep and remaining are the caller's to set. */
+int hsg_batch_init(const hsg_batch *b, void *stream);
+
+/* Up to n_sweeps sweeps of every chain (fewer where remaining says so), each with its
+ * own k_hits, n_or, renorm_every, flags, beta and sweep counter.  One launch; the
+ * work queue resets itself at the end, so the call can be captured in a HIP graph and
+ * replayed.  Chains must not overlap in memory except for shared couplings. */
+int hsg_batch_sweep(const hsg_batch *b, int32_t n_sweeps, void *stream);
+
+/* out_dev[c] = H of chain c, recomputed in binary64 (device array [n_chains]). */
+int hsg_batch_energy(const hsg_batch *b, double *out_dev, void *stream);
+
+/* Overlaps of chain pairs (same L): pairs_dev is a device array [n_pairs][2] of chain
+ * indices; out_dev [n_pairs][15] receives Q (9, row-major), m_a (3), m_b (3) as
+ * hsg_overlap does. */
+int hsg_batch_overlap(const hsg_batch *b, const int32_t *pairs_dev, int32_t n_pairs,
+                      double *out_dev, void *stream);
+
+/* Parallel tempering over temperature ladders of chains of a batch. */
+typedef struct hsg_pt {
+  int32_t n_ladders;
+  int32_t n_temps;
+  int32_t *chain_at_slot;     /* device [n_ladders][n_temps]: chain index in each slot */
+  const double *beta_of_slot; /* device [n_temps]: inverse temperature of slot t */
+  int32_t *accepted;          /* device [n_ladders][n_temps] or NULL: swaps accepted per pair */
+  uint32_t *round;            /* device [1]: index n of the next exchange round */
+  uint64_t seed;              /* Philox key of the exchange stream */
+} hsg_pt;
+
+/* One replica-exchange round on every ladder, n = *pt->round (then incremented on the
+ * device, so the call can be captured in a HIP graph): round n proposes the slot
+ * pairs (t, t+1) with t = n mod 2, t+2, ...; a pair with chains a, b is swapped with
+ * probability min(1, exp((beta_t - beta_{t+1}) (E_a - E_b))) using the uniform of
+ * Philox(key = seed, counter (t, n, ladder, 3)).  Swapped chains exchange slots; then
+ * b->beta[chain] is set from its slot for every chain of every ladder. */
+int hsg_pt_exchange(const hsg_pt *pt, const hsg_batch *b, void *stream);
+
+/* Overlap, slot by slot, between ladders: ladder_pairs_dev [n_pairs][2] of ladder
+ * indices; out_dev [n_pairs][n_temps][15] (as hsg_batch_overlap) for the chains that
+ * occupy slot t of the two ladders. */
+int hsg_pt_overlap(const hsg_pt *pt, const hsg_batch *b, const int32_t *ladder_pairs_dev,
+                   int32_t n_pairs, double *out_dev, void *stream);
+
 /* Message describing the last error returned to this thread ("" if none). */
 const char *hsg_last_error(void);
 

@@ -5,6 +5,10 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <algorithm>
+#include <utility>
+#include <vector>
+
 #include "hsg.h"
 #include "hsg_internal.h"
 
@@ -215,6 +219,150 @@ int hsg_overlap(const hsg_lattice* a, const hsg_lattice* b, double* out_dev, voi
                          "overlap");
   return device_status(hsg::launch_overlap<double>(a->L, a->spins, b->spins, part, out_dev, st),
                        "overlap");
+}
+
+/* ------------------------------------------------------------------- batched form */
+
+int hsg_batch_work_bytes(int32_t n_chains, size_t* work_bytes) {
+  if (n_chains < 1) return fail(HSG_EINVAL, "n_chains must be >= 1");
+  if (work_bytes) *work_bytes = hsg::batch_work_bytes(n_chains);
+  return HSG_OK;
+}
+
+int hsg_batch_check(const hsg_chain* c, int32_t n, int64_t spin_elems, int64_t J_elems) {
+  if (!c || n < 1) return fail(HSG_EINVAL, "chain table is empty");
+  std::vector<std::pair<int64_t, int64_t>> ranges;
+  ranges.reserve((size_t)n);
+  for (int32_t i = 0; i < n; ++i) {
+    const hsg_chain& ch = c[i];
+    if (ch.L < 2 || ch.L > HSG_BATCH_L_MAX || (ch.L & 1))
+      return fail(HSG_EINVAL, "chain %d: L must be even, 2 <= L <= %d (got %d)", (int)i,
+                  HSG_BATCH_L_MAX, (int)ch.L);
+    if (ch.k_hits < 0 || ch.n_or < 0 || ch.k_hits + ch.n_or < 1 || ch.k_hits > 0xFFFF ||
+        ch.n_or > 0x7FFF || ch.renorm_every < 0)
+      return fail(HSG_EINVAL, "chain %d: bad k_hits / n_or / renorm_every", (int)i);
+    if (ch.flags & ~(HSG_HEAT_BATH | HSG_CHAIN_INIT_J) || ch.reserved != 0)
+      return fail(HSG_EINVAL, "chain %d: unknown flags 0x%x", (int)i, (unsigned)ch.flags);
+    const int64_t n_el = (int64_t)3 * ch.L * ch.L * ch.L;
+    if (ch.spin_offset < 0 || ch.spin_offset + n_el > spin_elems)
+      return fail(HSG_EINVAL, "chain %d: spins outside the spin buffer", (int)i);
+    if (ch.J_offset < 0 || ch.J_offset + n_el > J_elems)
+      return fail(HSG_EINVAL, "chain %d: couplings outside the coupling buffer", (int)i);
+    ranges.emplace_back(ch.spin_offset, ch.spin_offset + n_el);
+  }
+  std::sort(ranges.begin(), ranges.end());
+  for (size_t i = 1; i < ranges.size(); ++i)
+    if (ranges[i].first < ranges[i - 1].second)
+      return fail(HSG_EINVAL, "spin ranges of two chains overlap");
+  return HSG_OK;
+}
+
+static int check_batch(const hsg_batch* b) {
+  if (!b) return fail(HSG_EINVAL, "batch descriptor is NULL");
+  if (b->n_chains < 1) return fail(HSG_EINVAL, "n_chains must be >= 1");
+  if (b->dtype != HSG_F32 && b->dtype != HSG_F64) return fail(HSG_EINVAL, "bad dtype");
+  if (!b->chains || !b->spins || !b->J || !b->beta || !b->E || !b->sweep || !b->order || !b->work)
+    return fail(HSG_EINVAL, "batch buffers chains, spins, J, beta, E, sweep, order, work must be set");
+  if (b->work_bytes < hsg::batch_work_bytes(b->n_chains))
+    return fail(HSG_EINVAL, "batch work buffer too small");
+  if (b->threads != 0 && (b->threads < 64 || b->threads > 1024 || (b->threads & 63)))
+    return fail(HSG_EINVAL, "threads must be 0 or a multiple of 64 in [64, 1024]");
+  if (b->max_groups < 0) return fail(HSG_EINVAL, "max_groups must be >= 0");
+  return HSG_OK;
+}
+
+static int compute_units() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
+
+int hsg_batch_init(const hsg_batch* b, void* stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  return device_status(b->dtype == HSG_F32 ? hsg::launch_batch_init<float>(b, st)
+                                           : hsg::launch_batch_init<double>(b, st),
+                       "batch init");
+}
+
+int hsg_batch_sweep(const hsg_batch* b, int32_t n_sweeps, void* stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (n_sweeps < 0) return fail(HSG_EINVAL, "n_sweeps must be >= 0");
+  if (n_sweeps == 0) return HSG_OK;
+  int groups = b->max_groups > 0 ? b->max_groups : 8 * compute_units();
+  if (groups > b->n_chains) groups = b->n_chains;
+  hipStream_t st = as_stream(stream);
+  return device_status(b->dtype == HSG_F32 ? hsg::launch_batch_sweep<float>(b, n_sweeps, groups, st)
+                                           : hsg::launch_batch_sweep<double>(b, n_sweeps, groups, st),
+                       "batch sweep");
+}
+
+int hsg_batch_energy(const hsg_batch* b, double* out_dev, void* stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (!out_dev) return fail(HSG_EINVAL, "out_dev is NULL");
+  hipStream_t st = as_stream(stream);
+  return device_status(b->dtype == HSG_F32 ? hsg::launch_batch_energy<float>(b, out_dev, st)
+                                           : hsg::launch_batch_energy<double>(b, out_dev, st),
+                       "batch energy");
+}
+
+int hsg_batch_overlap(const hsg_batch* b, const int32_t* pairs_dev, int32_t n_pairs,
+                      double* out_dev, void* stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (!pairs_dev || !out_dev || n_pairs < 0) return fail(HSG_EINVAL, "bad pairs or output");
+  if (n_pairs == 0) return HSG_OK;
+  hipStream_t st = as_stream(stream);
+  return device_status(
+      b->dtype == HSG_F32 ? hsg::launch_batch_overlap<float>(b, pairs_dev, n_pairs, out_dev, st)
+                          : hsg::launch_batch_overlap<double>(b, pairs_dev, n_pairs, out_dev, st),
+      "batch overlap");
+}
+
+static int check_pt(const hsg_pt* pt) {
+  if (!pt) return fail(HSG_EINVAL, "ladder descriptor is NULL");
+  if (pt->n_ladders < 1 || pt->n_temps < 1 || pt->n_temps > 65535)
+    return fail(HSG_EINVAL, "need n_ladders >= 1 and 1 <= n_temps <= 65535");
+  if (!pt->chain_at_slot || !pt->beta_of_slot)
+    return fail(HSG_EINVAL, "chain_at_slot and beta_of_slot must be set");
+  return HSG_OK;
+}
+
+int hsg_pt_exchange(const hsg_pt* pt, const hsg_batch* b, void* stream) {
+  int rc = check_pt(pt);
+  if (rc) return rc;
+  rc = check_batch(b);
+  if (rc) return rc;
+  if (!pt->round) return fail(HSG_EINVAL, "round counter must be set");
+  return device_status(hsg::launch_pt_exchange(pt, b, as_stream(stream)), "exchange");
+}
+
+int hsg_pt_overlap(const hsg_pt* pt, const hsg_batch* b, const int32_t* ladder_pairs_dev,
+                   int32_t n_pairs, double* out_dev, void* stream) {
+  int rc = check_pt(pt);
+  if (rc) return rc;
+  rc = check_batch(b);
+  if (rc) return rc;
+  if (!ladder_pairs_dev || !out_dev || n_pairs < 0) return fail(HSG_EINVAL, "bad pairs or output");
+  if (n_pairs == 0) return HSG_OK;
+  if (pt->n_temps > 65535) return fail(HSG_EINVAL, "too many temperatures");
+  hipStream_t st = as_stream(stream);
+  return device_status(
+      b->dtype == HSG_F32
+          ? hsg::launch_pt_overlap<float>(pt, b, ladder_pairs_dev, n_pairs, out_dev, st)
+          : hsg::launch_pt_overlap<double>(pt, b, ladder_pairs_dev, n_pairs, out_dev, st),
+      "ladder overlap");
 }
 
 }  // extern "C"

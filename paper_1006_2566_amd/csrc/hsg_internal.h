@@ -43,7 +43,7 @@ struct Planes {
 };
 
 template <typename R>
-inline Planes<R> planes_of(void* base, int64_t half_sites) {
+__host__ __device__ inline Planes<R> planes_of(void* base, int64_t half_sites) {
   Planes<R> out;
   for (int k = 0; k < 6; ++k) out.p[k] = (R*)base + (int64_t)k * half_sites;
   return out;
@@ -91,6 +91,29 @@ template <typename R>
 hipError_t launch_overlap(int32_t L, const void* a, const void* b, double* partials,
                           double* out, hipStream_t stream);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t stream);
+
+}  // namespace hsg
+
+struct hsg_batch;
+struct hsg_pt;
+
+namespace hsg {
+
+size_t batch_work_bytes(int32_t n_chains);
+template <typename R>
+hipError_t launch_batch_init(const hsg_batch* b, hipStream_t st);
+template <typename R>
+hipError_t launch_batch_sweep(const hsg_batch* b, int32_t n_sweeps, int32_t groups,
+                              hipStream_t st);
+template <typename R>
+hipError_t launch_batch_energy(const hsg_batch* b, double* out, hipStream_t st);
+template <typename R>
+hipError_t launch_batch_overlap(const hsg_batch* b, const int32_t* pairs, int32_t n_pairs,
+                                double* out, hipStream_t st);
+template <typename R>
+hipError_t launch_pt_overlap(const hsg_pt* pt, const hsg_batch* b, const int32_t* ladder_pairs,
+                             int32_t n_pairs, double* out, hipStream_t st);
+hipError_t launch_pt_exchange(const hsg_pt* pt, const hsg_batch* b, hipStream_t st);
 hipError_t launch_copy_double(const double* src, double* dst, hipStream_t stream);
 
 }  // namespace hsg

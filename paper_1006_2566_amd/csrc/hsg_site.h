@@ -1,0 +1,200 @@
+// One colour-pass update of one site: gather the local field of eq. (2) from the six
+// other-colour neighbours, then apply k Metropolis hits, k heat-bath draws or one
+// over-relaxation step.  Shared by the single-lattice colour-pass kernel and the
+// batched kernel, so a lattice gives the same bits alone or inside a batch.
+#pragma once
+
+#include "hsg_device.h"
+#include "hsg_internal.h"
+
+namespace hsg {
+
+// Position of internal element e (0 <= e < N) of the colour-split layout.
+struct SiteOf {
+  int32_t c, xh, y, z, x;
+  int64_t ic;         // index within the colour's planes
+  uint32_t canon;     // x + L*y + L*L*z
+};
+
+__device__ __forceinline__ SiteOf site_of(int64_t e, int32_t L) {
+  const int32_t Lh = L / 2;
+  const int64_t Nh = (int64_t)Lh * L * L;
+  SiteOf s;
+  s.c = e >= Nh ? 1 : 0;
+  s.ic = e - (int64_t)s.c * Nh;
+  s.xh = (int32_t)(s.ic % Lh);
+  const int64_t r = s.ic / Lh;
+  s.y = (int32_t)(r % L);
+  s.z = (int32_t)(r / L);
+  s.x = 2 * s.xh + ((s.y + s.z + s.c) & 1);
+  s.canon = (uint32_t)s.x + (uint32_t)L * ((uint32_t)s.y + (uint32_t)L * (uint32_t)s.z);
+  return s;
+}
+
+// Random initial state of internal element e (0 <= e < N) of an L^3 lattice:
+// spin uniform on the sphere from Philox tag 1; couplings (when J is not NULL) by
+// Box-Muller from tag 2: (u0,u1) -> Jx, Jy; (u2,u3) -> Jz.  Counter (0, site, 0, tag).
+template <typename R>
+__device__ __forceinline__ void init_site(int32_t L, int64_t e, uint32_t k0, uint32_t k1,
+                                          R* spins, R* J, uint32_t jk0, uint32_t jk1) {
+  const int64_t Nh = (int64_t)L * L * L / 2;
+  const SiteOf st = site_of(e, L);
+  const Word4 ws = philox10(0u, st.canon, 0u, kTagInitSpin, k0, k1);
+  const Vec3<R> s = sphere_point(unit_uniform<R>(ws.w0), unit_uniform<R>(ws.w1));
+  const int64_t base = (int64_t)3 * st.c * Nh + st.ic;
+  spins[base] = s.x;
+  spins[base + Nh] = s.y;
+  spins[base + 2 * Nh] = s.z;
+  if (!J) return;
+  const Word4 wj = philox10(0u, st.canon, 0u, kTagInitJ, jk0, jk1);
+  R sn, cs;
+  const R r01 = dev_sqrt((R)-2 * dev_log(unit_uniform<R>(wj.w0)));
+  sincos_2pi(unit_uniform<R>(wj.w1), sn, cs);
+  J[base] = r01 * cs;
+  J[base + Nh] = r01 * sn;
+  const R r23 = dev_sqrt((R)-2 * dev_log(unit_uniform<R>(wj.w2)));
+  sincos_2pi(unit_uniform<R>(wj.w3), sn, cs);
+  J[base + 2 * Nh] = r23 * cs;
+}
+
+// Spin accesses, optionally with the non-temporal hint.
+template <bool NT, typename R>
+__device__ __forceinline__ R load_spin(const R* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  return *p;
+}
+template <bool NT, typename R>
+__device__ __forceinline__ void store_spin(R v, R* p) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
+
+// Where a site sits: colour c, column xh of its colour row, row y, plane z.
+struct SitePos {
+  int32_t L, Lh, c, xh, y, z;
+};
+
+// Monte Carlo stream of the site: Philox key and the uniform counter words.
+template <typename R>
+struct HitCtx {
+  R beta;
+  uint32_t sweep, phase;
+  int32_t k_hits;
+  uint32_t seed_lo, seed_hi;
+};
+
+// Updates the site in place; returns the sum of the accepted energy changes.
+template <typename R, PassMode MODE, bool NT>
+__device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R>& J,
+                                              const SitePos& q, const HitCtx<R>& hc) {
+  const int32_t L = q.L, Lh = q.Lh, c = q.c, xh = q.xh, y = q.y, z = q.z;
+  const int32_t p = (y + z + c) & 1;  // x = 2 xh + p
+  const int32_t ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+  const int32_t zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
+  const int32_t row = Lh * (y + L * z);
+  const int32_t own = row + xh;
+  // other-colour neighbours: x+1 and x-1 in the same row, y+-1 and z+-1 at the same xh
+  const int32_t n_px = row + (p ? (xh + 1 == Lh ? 0 : xh + 1) : xh);
+  const int32_t n_mx = row + (p ? xh : (xh == 0 ? Lh - 1 : xh - 1));
+  const int32_t n_py = Lh * (yp + L * z) + xh, n_my = Lh * (ym + L * z) + xh;
+  const int32_t n_pz = Lh * (y + L * zp) + xh, n_mz = Lh * (y + L * zm) + xh;
+  const int oc = 3 * c, nc = 3 * (1 - c);
+
+  // couplings of the six bonds: +x,+y,+z stored at the site, -x,-y,-z at the neighbour
+  const R j_px = J.p[oc + 0][own], j_mx = J.p[nc + 0][n_mx];
+  const R j_py = J.p[oc + 1][own], j_my = J.p[nc + 1][n_my];
+  const R j_pz = J.p[oc + 2][own], j_mz = J.p[nc + 2][n_mz];
+  R hcomp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const R* sn = S.p[nc + k];
+    R acc = j_px * load_spin<NT>(sn + n_px);
+    acc = dev_fma(j_mx, load_spin<NT>(sn + n_mx), acc);
+    acc = dev_fma(j_py, load_spin<NT>(sn + n_py), acc);
+    acc = dev_fma(j_my, load_spin<NT>(sn + n_my), acc);
+    acc = dev_fma(j_pz, load_spin<NT>(sn + n_pz), acc);
+    acc = dev_fma(j_mz, load_spin<NT>(sn + n_mz), acc);
+    hcomp[k] = acc;
+  }
+  const Vec3<R> h{hcomp[0], hcomp[1], hcomp[2]};
+  Vec3<R> s{load_spin<NT>(S.p[oc + 0] + own), load_spin<NT>(S.p[oc + 1] + own),
+            load_spin<NT>(S.p[oc + 2] + own)};
+
+  double dE_sum = 0.0;
+  if constexpr (MODE == PassMode::OverRelax) {
+    s = reflect(s, h);
+  } else {
+    const uint32_t site = (uint32_t)(2 * xh + p) + (uint32_t)L * (uint32_t)(y + L * z);
+    const uint32_t tag = MODE == PassMode::Metropolis ? kTagMetropolis : kTagHeatBath;
+    R sh = dot3(s, h);
+    for (int32_t j = 0; j < hc.k_hits; ++j) {
+      const Word4 w = philox10(hc.sweep, site, (hc.phase << 16) | (uint32_t)j, tag, hc.seed_lo,
+                               hc.seed_hi);
+      Vec3<R> trial;
+      if constexpr (MODE == PassMode::Metropolis) {
+        trial = sphere_point_words<R>(w.w0, w.w1);
+      } else {
+        trial = heat_bath_point(h, hc.beta, unit_uniform<R>(w.w0), unit_uniform<R>(w.w1));
+      }
+      const R th = dot3(trial, h);
+      const R dE = sh - th;
+      bool accept = true;
+      if constexpr (MODE == PassMode::Metropolis) {
+        const R u2 = unit_uniform<R>(w.w2);
+        accept = (dE <= (R)0) || (u2 < accept_prob(-hc.beta * dE));
+      }
+      if (accept) {
+        s = trial;
+        sh = th;
+        dE_sum += (double)dE;
+      }
+    }
+  }
+  store_spin<NT>(s.x, S.p[oc + 0] + own);
+  store_spin<NT>(s.y, S.p[oc + 1] + own);
+  store_spin<NT>(s.z, S.p[oc + 2] + own);
+  return dE_sum;
+}
+
+// sigma <- sigma / |sigma| for the spin at index e of colour c (N/2 = Nh per colour).
+template <typename R>
+__device__ __forceinline__ void renormalise_spin(const Planes<R>& S, int c, int64_t e) {
+  const Vec3<R> s{S.p[3 * c][e], S.p[3 * c + 1][e], S.p[3 * c + 2][e]};
+  const R n = dev_sqrt(dot3(s, s));
+  S.p[3 * c][e] = dev_div(s.x, n);
+  S.p[3 * c + 1][e] = dev_div(s.y, n);
+  S.p[3 * c + 2][e] = dev_div(s.z, n);
+}
+
+// sigma_i . h_i of the colour-0 site (xh, y, z) in binary64.  Every bond has exactly
+// one colour-0 end (L even), so H = -(sum of this over the colour-0 sites).
+template <typename R>
+__device__ __forceinline__ double colour0_bond_sum(const R* spins, const R* J, int64_t Nh,
+                                                   int32_t L, int32_t Lh, int32_t xh, int32_t y,
+                                                   int32_t z) {
+  const int32_t p = (y + z) & 1;
+  const int32_t ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+  const int32_t zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
+  const int64_t row = (int64_t)Lh * (y + (int64_t)L * z);
+  const int64_t own = row + xh;
+  const int64_t nb[6] = {row + (p ? (xh + 1 == Lh ? 0 : xh + 1) : xh),
+                         row + (p ? xh : (xh == 0 ? Lh - 1 : xh - 1)),
+                         (int64_t)Lh * (yp + (int64_t)L * z) + xh,
+                         (int64_t)Lh * (ym + (int64_t)L * z) + xh,
+                         (int64_t)Lh * (y + (int64_t)L * zp) + xh,
+                         (int64_t)Lh * (y + (int64_t)L * zm) + xh};
+  const double jb[6] = {(double)J[own],      (double)J[3 * Nh + nb[1]], (double)J[Nh + own],
+                        (double)J[4 * Nh + nb[3]], (double)J[2 * Nh + own],
+                        (double)J[5 * Nh + nb[5]]};
+  double e_site = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    double hk = 0.0;
+    for (int d = 0; d < 6; ++d) hk = fma(jb[d], (double)spins[(3 + k) * Nh + nb[d]], hk);
+    e_site = fma((double)spins[k * Nh + own], hk, e_site);
+  }
+  return e_site;
+}
+
+}  // namespace hsg

@@ -4,32 +4,11 @@
 // favour simple grid-stride loops over the tuned tiling of the colour passes.
 #include "hsg_device.h"
 #include "hsg_internal.h"
+#include "hsg_site.h"
 
 namespace hsg {
 
 namespace {
-
-// Position of internal element e (0 <= e < N) of the colour-split layout.
-struct SiteOf {
-  int32_t c, xh, y, z, x;
-  int64_t ic;         // index within the colour's planes
-  uint32_t canon;     // x + L*y + L*L*z
-};
-
-__device__ __forceinline__ SiteOf site_of(int64_t e, int32_t L) {
-  const int32_t Lh = L / 2;
-  const int64_t Nh = (int64_t)Lh * L * L;
-  SiteOf s;
-  s.c = e >= Nh ? 1 : 0;
-  s.ic = e - (int64_t)s.c * Nh;
-  s.xh = (int32_t)(s.ic % Lh);
-  const int64_t r = s.ic / Lh;
-  s.y = (int32_t)(r % L);
-  s.z = (int32_t)(r / L);
-  s.x = 2 * s.xh + ((s.y + s.z + s.c) & 1);
-  s.canon = (uint32_t)s.x + (uint32_t)L * ((uint32_t)s.y + (uint32_t)L * (uint32_t)s.z);
-  return s;
-}
 
 inline unsigned grid_for(int64_t n, int threads) {
   const int64_t b = (n + threads - 1) / threads;
@@ -39,26 +18,10 @@ inline unsigned grid_for(int64_t n, int threads) {
 template <typename R>
 __global__ __launch_bounds__(256) void init_kernel(int32_t L, uint32_t k0, uint32_t k1, R* spins,
                                                    R* J) {
-  const int64_t N = (int64_t)L * L * L, Nh = N / 2;
+  const int64_t N = (int64_t)L * L * L;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < N;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const SiteOf st = site_of(e, L);
-    const Word4 ws = philox10(0u, st.canon, 0u, kTagInitSpin, k0, k1);
-    const Vec3<R> s = sphere_point(unit_uniform<R>(ws.w0), unit_uniform<R>(ws.w1));
-    const int64_t base = (int64_t)3 * st.c * Nh + st.ic;
-    spins[base] = s.x;
-    spins[base + Nh] = s.y;
-    spins[base + 2 * Nh] = s.z;
-    // Box-Muller: (u0,u1) -> Jx, Jy; (u2,u3) -> Jz
-    const Word4 wj = philox10(0u, st.canon, 0u, kTagInitJ, k0, k1);
-    R sn, cs;
-    const R r01 = dev_sqrt((R)-2 * dev_log(unit_uniform<R>(wj.w0)));
-    sincos_2pi(unit_uniform<R>(wj.w1), sn, cs);
-    J[base] = r01 * cs;
-    J[base + Nh] = r01 * sn;
-    const R r23 = dev_sqrt((R)-2 * dev_log(unit_uniform<R>(wj.w2)));
-    sincos_2pi(unit_uniform<R>(wj.w3), sn, cs);
-    J[base + 2 * Nh] = r23 * cs;
+    init_site<R>(L, e, k0, k1, spins, J, k0, k1);
   }
 }
 
@@ -136,26 +99,7 @@ __global__ __launch_bounds__(kReduceThreads) void energy_kernel(int32_t L, const
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < Nh;
        e += (int64_t)gridDim.x * blockDim.x) {
     const SiteOf st = site_of(e, L);  // colour 0
-    const int32_t y = st.y, z = st.z, xh = st.xh, p = st.x & 1;
-    const int32_t ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-    const int32_t zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
-    const int64_t row = (int64_t)Lh * (y + (int64_t)L * z);
-    const int64_t own = row + xh;
-    const int64_t nb[6] = {row + (p ? (xh + 1 == Lh ? 0 : xh + 1) : xh),
-                           row + (p ? xh : (xh == 0 ? Lh - 1 : xh - 1)),
-                           (int64_t)Lh * (yp + (int64_t)L * z) + xh,
-                           (int64_t)Lh * (ym + (int64_t)L * z) + xh,
-                           (int64_t)Lh * (y + (int64_t)L * zp) + xh,
-                           (int64_t)Lh * (y + (int64_t)L * zm) + xh};
-    const double jb[6] = {(double)J[own], (double)J[3 * Nh + nb[1]], (double)J[Nh + own],
-                          (double)J[4 * Nh + nb[3]], (double)J[2 * Nh + own],
-                          (double)J[5 * Nh + nb[5]]};
-    double e_site = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      double hk = 0.0;
-      for (int d = 0; d < 6; ++d) hk = fma(jb[d], (double)spins[(3 + k) * Nh + nb[d]], hk);
-      e_site = fma((double)spins[k * Nh + own], hk, e_site);
-    }
+    const double e_site = colour0_bond_sum(spins, J, Nh, L, Lh, st.xh, st.y, st.z);
     v[0] += e_site;
   }
   block_partials(v, 1, partials);

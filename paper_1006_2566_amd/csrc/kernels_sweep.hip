@@ -13,6 +13,7 @@
 
 #include "hsg_device.h"
 #include "hsg_internal.h"
+#include "hsg_site.h"
 
 namespace hsg {
 
@@ -51,19 +52,6 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
   return xcd * q + min(xcd, r) + local;
 }
 
-// Spin accesses, optionally with the non-temporal hint (streamed past the caches so
-// that the couplings, reused by every pass, keep their place).
-template <bool NT, typename R>
-__device__ __forceinline__ R load_spin(const R* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p);
-  return *p;
-}
-template <bool NT, typename R>
-__device__ __forceinline__ void store_spin(R v, R* p) {
-  if constexpr (NT) __builtin_nontemporal_store(v, p);
-  else *p = v;
-}
-
 template <typename R, PassMode MODE, bool NT>
 __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
   const Geometry& g = a.g;
@@ -74,79 +62,18 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
   const int32_t ty = rest % g.tiles_y;
   const int32_t tz = rest / g.tiles_y;
   const int32_t t = (int32_t)threadIdx.x;
-  const int32_t xh = (tx << g.bx_log) + (t & ((1 << g.bx_log) - 1));
-  const int32_t y = (ty << g.by_log) + ((t >> g.bx_log) & ((1 << g.by_log) - 1));
-  const int32_t z = (tz << g.bz_log) + (t >> (g.bx_log + g.by_log));
-  const bool active = t < g.threads && xh < g.Lh && y < g.L && z < g.L;
+  SitePos q;
+  q.L = g.L;
+  q.Lh = g.Lh;
+  q.c = a.colour;
+  q.xh = (tx << g.bx_log) + (t & ((1 << g.bx_log) - 1));
+  q.y = (ty << g.by_log) + ((t >> g.bx_log) & ((1 << g.by_log) - 1));
+  q.z = (tz << g.bz_log) + (t >> (g.bx_log + g.by_log));
+  const bool active = t < g.threads && q.xh < g.Lh && q.y < g.L && q.z < g.L;
+  const HitCtx<R> hc{a.beta, a.sweep, a.phase, a.k_hits, a.seed_lo, a.seed_hi};
 
   double dE_sum = 0.0;
-  if (active) {
-    const int32_t L = g.L, Lh = g.Lh, c = a.colour;
-    const int32_t p = (y + z + c) & 1;  // x = 2 xh + p
-    const int32_t ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-    const int32_t zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
-    const int32_t row = Lh * (y + L * z);
-    const int32_t own = row + xh;
-    // other-colour neighbours: x+1 and x-1 in the same row, y+-1 and z+-1 at the same xh
-    const int32_t n_px = row + (p ? (xh + 1 == Lh ? 0 : xh + 1) : xh);
-    const int32_t n_mx = row + (p ? xh : (xh == 0 ? Lh - 1 : xh - 1));
-    const int32_t n_py = Lh * (yp + L * z) + xh, n_my = Lh * (ym + L * z) + xh;
-    const int32_t n_pz = Lh * (y + L * zp) + xh, n_mz = Lh * (y + L * zm) + xh;
-    const int oc = 3 * c, nc = 3 * (1 - c);
-
-    // couplings of the six bonds: +x,+y,+z stored at the site, -x,-y,-z at the neighbour
-    const R j_px = a.J.p[oc + 0][own], j_mx = a.J.p[nc + 0][n_mx];
-    const R j_py = a.J.p[oc + 1][own], j_my = a.J.p[nc + 1][n_my];
-    const R j_pz = a.J.p[oc + 2][own], j_mz = a.J.p[nc + 2][n_mz];
-    R hc[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const R* sn = a.spins.p[nc + k];
-      R acc = j_px * load_spin<NT>(sn + n_px);
-      acc = dev_fma(j_mx, load_spin<NT>(sn + n_mx), acc);
-      acc = dev_fma(j_py, load_spin<NT>(sn + n_py), acc);
-      acc = dev_fma(j_my, load_spin<NT>(sn + n_my), acc);
-      acc = dev_fma(j_pz, load_spin<NT>(sn + n_pz), acc);
-      acc = dev_fma(j_mz, load_spin<NT>(sn + n_mz), acc);
-      hc[k] = acc;
-    }
-    const Vec3<R> h{hc[0], hc[1], hc[2]};
-    Vec3<R> s{load_spin<NT>(a.spins.p[oc + 0] + own), load_spin<NT>(a.spins.p[oc + 1] + own),
-              load_spin<NT>(a.spins.p[oc + 2] + own)};
-
-    if constexpr (MODE == PassMode::OverRelax) {
-      s = reflect(s, h);
-    } else {
-      const uint32_t site = (uint32_t)(2 * xh + p) + (uint32_t)L * (uint32_t)(y + L * z);
-      const uint32_t tag = MODE == PassMode::Metropolis ? kTagMetropolis : kTagHeatBath;
-      R sh = dot3(s, h);
-      for (int32_t j = 0; j < a.k_hits; ++j) {
-        const Word4 w = philox10(a.sweep, site, (a.phase << 16) | (uint32_t)j, tag, a.seed_lo,
-                                 a.seed_hi);
-        Vec3<R> trial;
-        if constexpr (MODE == PassMode::Metropolis) {
-          trial = sphere_point_words<R>(w.w0, w.w1);
-        } else {
-          trial = heat_bath_point(h, a.beta, unit_uniform<R>(w.w0), unit_uniform<R>(w.w1));
-        }
-        const R th = dot3(trial, h);
-        const R dE = sh - th;
-        bool accept = true;
-        if constexpr (MODE == PassMode::Metropolis) {
-          const R u2 = unit_uniform<R>(w.w2);
-          accept = (dE <= (R)0) || (u2 < accept_prob(-a.beta * dE));
-        }
-        if (accept) {
-          s = trial;
-          sh = th;
-          dE_sum += (double)dE;
-        }
-      }
-    }
-    store_spin<NT>(s.x, a.spins.p[oc + 0] + own);
-    store_spin<NT>(s.y, a.spins.p[oc + 1] + own);
-    store_spin<NT>(s.z, a.spins.p[oc + 2] + own);
-  }
+  if (active) dE_sum = update_site<R, MODE, NT>(a.spins, a.J, q, hc);
 
   if constexpr (MODE != PassMode::OverRelax) {
     __shared__ double wave_part[4];

@@ -7,6 +7,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -116,3 +117,75 @@ def test_product_path_has_no_fallback(tmp_path, monkeypatch):
     with pytest.raises(ImportError):
         m.lib()
     importlib.reload(m)
+
+
+# ------------------------------------------------------------------ batched form
+def _table(B, rows):
+    import numpy as np
+    t = np.zeros(len(rows), dtype=B.CHAIN_DTYPE)
+    for i, r in enumerate(rows):
+        t[i] = r
+    return t
+
+
+@pytest.mark.parametrize("rows,spin_elems,J_elems,msg", [
+    ([(0, 0, 1, 1, 7, 1, 0, 0, 0, 0)], 10 ** 6, 10 ** 6, b"L must be even"),
+    ([(0, 0, 1, 1, 258, 1, 0, 0, 0, 0)], 10 ** 9, 10 ** 9, b"L must be even"),
+    ([(0, 0, 1, 1, 8, 0, 0, 0, 0, 0)], 10 ** 6, 10 ** 6, b"k_hits"),
+    ([(0, 0, 1, 1, 8, 1, 0, 0, 64, 0)], 10 ** 6, 10 ** 6, b"flags"),
+    ([(0, 0, 1, 1, 8, 1, 0, 0, 0, 0)], 1000, 10 ** 6, b"spin buffer"),
+    ([(0, 10, 1, 1, 8, 1, 0, 0, 0, 0)], 10 ** 6, 1536, b"coupling buffer"),
+    ([(0, 0, 1, 1, 8, 1, 0, 0, 0, 0), (1000, 0, 1, 1, 8, 1, 0, 0, 0, 0)], 10 ** 6, 10 ** 6,
+     b"overlap"),
+])
+def test_batch_check_rejects(hsg, rows, spin_elems, J_elems, msg):
+    from paper_1006_2566_amd import batch as B
+    B._bind()
+    t = _table(B, rows)
+    lib = hsg.lib()
+    assert lib.hsg_batch_check(t.ctypes.data_as(ctypes.c_void_p), len(rows), spin_elems,
+                               J_elems) == -1
+    assert msg in lib.hsg_last_error()
+
+
+def test_batch_check_accepts_shared_couplings(hsg):
+    from paper_1006_2566_amd import batch as B
+    B._bind()
+    n = 3 * 8 ** 3
+    t = _table(B, [(0, 0, 1, 1, 8, 1, 0, 0, 8, 0), (n, 0, 2, 1, 8, 4, 1, 10, 1, 0)])
+    assert hsg.lib().hsg_batch_check(t.ctypes.data_as(ctypes.c_void_p), 2, 2 * n, n) == 0
+
+
+def test_batch_descriptor_validation(hsg):
+    from paper_1006_2566_amd import batch as B
+    B._bind()
+    lib = hsg.lib()
+    d = B._Batch(2, 0, 0x10, 0x20, 0x30, 0x40, 0x50, 0x60, None, 0x70, 0x80, 256, 96, 0)
+    assert lib.hsg_batch_sweep(ctypes.byref(d), 1, None) == -1  # threads not a multiple of 64
+    d.threads = 256
+    d.work_bytes = 8
+    assert lib.hsg_batch_sweep(ctypes.byref(d), 1, None) == -1
+    assert b"work buffer" in lib.hsg_last_error()
+    d.work_bytes = 256
+    d.E = None
+    assert lib.hsg_batch_init(ctypes.byref(d), None) == -1
+    p = B._PT(0, 4, 0x10, 0x20, None, 0x30, 1)
+    d.E = 0x50
+    assert lib.hsg_pt_exchange(ctypes.byref(p), ctypes.byref(d), None) == -1
+    p = B._PT(2, 4, 0x10, 0x20, None, None, 1)
+    assert lib.hsg_pt_exchange(ctypes.byref(p), ctypes.byref(d), None) == -1
+    assert b"round" in lib.hsg_last_error()
+
+
+def test_pt_workload_shape():
+    from paper_1006_2566_amd import batch as B
+    specs, ladders, betas, pairs = B.pt_workload()
+    assert len(specs) == 256 * 2 * 24 and ladders.shape == (512, 24) and pairs.shape == (256, 2)
+    assert abs(1 / betas[0] - 0.12) < 1e-12 and abs(1 / betas[-1] - 0.5) < 1e-12
+    # geometric: constant ratio of successive temperatures
+    T = 1 / betas
+    assert np.allclose(T[1:] / T[:-1], (0.5 / 0.12) ** (1 / 23))
+    Ls = {s.L for s in specs}
+    assert Ls <= {16, 24, 32, 48}
+    # a sample's 48 chains share one coupling group and one L
+    assert len({(s.J_group, s.L) for s in specs}) == 256
