@@ -45,6 +45,11 @@ def parse():
                     help="timed cycles (100 sweeps each) of the batched tempering workload; "
                          "0 skips that leg")
     ap.add_argument("--batch-threads", type=int, default=256)
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the served stream (0 skips that leg)")
+    ap.add_argument("--serve-budget-mb", type=int, default=8192,
+                    help="device memory for resident lattices of the served stream")
+    ap.add_argument("--serve-step", type=int, default=16, help="sweeps per scheduling step")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
                          "(calibrates FETCH_SIZE / WRITE_SIZE), then 2 sweeps of the headline "
@@ -121,6 +126,36 @@ def batched_leg(args, torch):
             "speedup_vs_plain": upd / upd_plain,
             "exchange_acceptance_per_pair_round": acc,
             "threads": args.batch_threads}
+
+
+def served_leg(args, torch):
+    """Request stream: Poisson arrivals at 200 per second, L uniform in
+    {8,16,32,64,96}, T uniform in [0.1,1], sweeps log-uniform in [100,10000], k in
+    {1,4}, binary32, admitted by device-memory footprint, lattices resident between
+    steps, continuous batching; latency = completion - arrival (wall clock)."""
+    import numpy as np
+
+    from paper_1006_2566_amd import serve as S
+
+    trace = S.poisson_trace(n=args.serve_requests, rate=200.0, seed=1)
+    srv = S.Server(hbm_budget=args.serve_budget_mb << 20, n_slots=2048,
+                   step_sweeps=args.serve_step)
+    srv.run([S.Request(rid=-1, seed=1, L=8, T=1.0, sweeps=2, k=1)], realtime=False)  # load kernels
+    t0 = time.perf_counter()
+    res = srv.run(trace, realtime=True)
+    wall = time.perf_counter() - t0
+    upd = float(sum(r.L ** 3 * r.sweeps * r.k for r in trace))
+    offered = upd / trace[-1].arrival / 1e9
+    st = S.latency_stats(res)
+    return {"workload": f"{len(trace)} requests, Poisson 200/s, L in {{8,16,32,64,96}}, "
+                        "T in [0.1,1], sweeps log-uniform [100,1e4], k in {1,4}, binary32",
+            "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
+            "mean_latency_s": st["mean_s"], "wall_s": wall,
+            "spin_updates_per_ns": upd / (wall * 1e9),
+            "offered_updates_per_ns": offered, "budget_mb": args.serve_budget_mb,
+            "step_sweeps": args.serve_step,
+            "scheduler": {k: (round(v, 3) if isinstance(v, float) else v)
+                          for k, v in srv.stats.items()}}
 
 
 def cpu_baseline(args):
@@ -213,6 +248,9 @@ def main():
         del lat
         torch.cuda.empty_cache()
         rec["batched"] = batched_leg(args, torch)
+    if args.serve_requests > 0:
+        torch.cuda.empty_cache()
+        rec["served"] = served_leg(args, torch)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args)
     print(json.dumps(rec), flush=True)

@@ -52,11 +52,10 @@ extern "C" {
 
 #define HSG_L_MAX 1290 /* largest L: N = L^3 < 2^31 keeps every site index in 32 bits */
 
-/* Sweep flags (hsg_sweep_params.flags).  The last two change only the order in which
+/* Sweep flags (hsg_sweep_params.flags).  HSG_SNAKE changes only the order in which
  * memory is touched, never a result. */
-#define HSG_HEAT_BATH 1    /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
-#define HSG_SNAKE 2        /* successive colour passes walk the lattice in opposite z order */
-#define HSG_STREAM_SPINS 4 /* spin loads/stores carry the non-temporal hint */
+#define HSG_HEAT_BATH 1 /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
+#define HSG_SNAKE 2     /* successive colour passes walk the lattice in opposite z order */
 
 typedef struct hsg_lattice {
   int32_t L;         /* even, 2 <= L <= HSG_L_MAX */
@@ -76,7 +75,7 @@ typedef struct hsg_sweep_params {
   int32_t n_or;         /* over-relaxation phases per sweep, >= 0; k_hits + n_or >= 1 */
   int32_t renorm_every; /* R > 0: after sweep s with (s+1) % R == 0 every spin is
                            divided by its length; 0 = never */
-  int32_t flags;        /* OR of HSG_HEAT_BATH, HSG_SNAKE, HSG_STREAM_SPINS */
+  int32_t flags;        /* OR of HSG_HEAT_BATH and HSG_SNAKE */
 } hsg_sweep_params;
 
 /* Sizes of the three device buffers of an L^3 lattice of the given dtype.  Any
@@ -156,15 +155,10 @@ typedef struct hsg_batch {
   int32_t *remaining;      /* device [n_chains] or NULL: sweeps each chain still has to run;
                               a launch runs min(n_sweeps, remaining) and subtracts them */
   const int32_t *order;    /* device [n_chains]: a permutation, the order in which
-                              workgroups take the chains (largest L first balances load) */
-  void *work;              /* device scratch of at least hsg_batch_work_bytes bytes */
-  size_t work_bytes;
+                              workgroups are dispatched (largest L first balances load) */
   int32_t threads;         /* threads per workgroup: a multiple of 64 up to 1024 (0 = 256) */
-  int32_t max_groups;      /* workgroups of the persistent grid (0 = 8 per compute unit) */
+  int32_t reserved;        /* must be 0 */
 } hsg_batch;
-
-/* Scratch bytes a batch of n_chains needs (queue counters). */
-int hsg_batch_work_bytes(int32_t n_chains, size_t *work_bytes);
 
 /* Host-side check of a chain table before it is copied to the device: every chain
  * has an even 2 <= L <= HSG_BATCH_L_MAX, k_hits/n_or/renorm_every/flags as
@@ -195,6 +189,28 @@ int hsg_batch_energy(const hsg_batch *b, double *out_dev, void *stream);
  * hsg_overlap does. */
 int hsg_batch_overlap(const hsg_batch *b, const int32_t *pairs_dev, int32_t n_pairs,
                       double *out_dev, void *stream);
+
+/* Tiles for hsg_batch_pass_sweep: for each chain listed in active[0..n_active), its
+ * colour-site range [0, L^3/2) split into runs of tile_sites (<= 1024) consecutive
+ * colour sites; tiles_out[2*t] = chain, tiles_out[2*t+1] = first colour-site index.
+ * Host memory.  *n_tiles receives the count; HSG_EINVAL if it would exceed capacity. */
+int hsg_batch_tiles(const hsg_chain *host_chains, int32_t n_chains, const int32_t *active,
+                    int32_t n_active, int32_t tile_sites, int32_t *tiles_out, int32_t capacity,
+                    int32_t *n_tiles);
+
+/* Up to n_sweeps sweeps of the chains that own tiles, as a sequence of launches: one
+ * per colour pass, each covering the tiles of every listed chain (so lattices too large
+ * for one workgroup still fill the GPU, and lattices of every size share launches),
+ * then one per sweep for the renormalisation when renorm != 0, then a finishing launch
+ * that advances b->sweep and b->remaining.  Chain c runs min(n_sweeps, remaining[c])
+ * sweeps (b->remaining must be set).  All listed chains follow one pass schedule:
+ * phases 0..max n_or, a chain skipping phases it does not have.  Energy changes are
+ * added to b->E with device atomics (the order of the binary64 additions, and so the
+ * last bits of E, may vary between runs; spins do not).  tiles_dev is a device copy
+ * of the table from hsg_batch_tiles; tile_sites must match it. */
+int hsg_batch_pass_sweep(const hsg_batch *b, const int32_t *tiles_dev, int32_t n_tiles,
+                         int32_t tile_sites, int32_t max_n_or, int32_t renorm, int32_t n_sweeps,
+                         void *stream);
 
 /* Parallel tempering over temperature ladders of chains of a batch. */
 typedef struct hsg_pt {

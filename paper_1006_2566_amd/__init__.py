@@ -26,7 +26,6 @@ LIB_PATH = os.path.join(_HERE, "libhsg.so")
 HSG_F32, HSG_F64 = 0, 1
 HSG_HEAT_BATH = 1
 HSG_SNAKE = 2
-HSG_STREAM_SPINS = 4
 # traversal flags the benchmark uses unless told otherwise (order only; results unchanged)
 DEFAULT_SWEEP_FLAGS = HSG_SNAKE
 L_MAX = 1290

@@ -29,8 +29,7 @@ class _Batch(ctypes.Structure):
                 ("chains", ctypes.c_void_p), ("spins", ctypes.c_void_p), ("J", ctypes.c_void_p),
                 ("beta", ctypes.c_void_p), ("E", ctypes.c_void_p), ("sweep", ctypes.c_void_p),
                 ("remaining", ctypes.c_void_p), ("order", ctypes.c_void_p),
-                ("work", ctypes.c_void_p), ("work_bytes", ctypes.c_size_t),
-                ("threads", ctypes.c_int32), ("max_groups", ctypes.c_int32)]
+                ("threads", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class _PT(ctypes.Structure):
@@ -50,7 +49,6 @@ def _bind():
     L = lib()
     P, I32 = ctypes.c_void_p, ctypes.c_int32
     BP, PP = ctypes.POINTER(_Batch), ctypes.POINTER(_PT)
-    L.hsg_batch_work_bytes.argtypes = [I32, ctypes.POINTER(ctypes.c_size_t)]
     L.hsg_batch_check.argtypes = [P, I32, ctypes.c_int64, ctypes.c_int64]
     L.hsg_batch_init.argtypes = [BP, P]
     L.hsg_batch_sweep.argtypes = [BP, I32, P]
@@ -58,7 +56,7 @@ def _bind():
     L.hsg_batch_overlap.argtypes = [BP, P, I32, P, P]
     L.hsg_pt_exchange.argtypes = [PP, BP, P]
     L.hsg_pt_overlap.argtypes = [PP, BP, P, I32, P, P]
-    for name in ("hsg_batch_work_bytes", "hsg_batch_check", "hsg_batch_init", "hsg_batch_sweep",
+    for name in ("hsg_batch_check", "hsg_batch_init", "hsg_batch_sweep",
                  "hsg_batch_energy", "hsg_batch_overlap", "hsg_pt_exchange", "hsg_pt_overlap"):
         getattr(L, name).restype = ctypes.c_int
     _bound = True
@@ -91,7 +89,7 @@ class Batch:
     """Chains resident on the GPU, advanced together by ``sweep``."""
 
     def __init__(self, specs: list[ChainSpec], dtype: torch.dtype = torch.float32,
-                 device: str | torch.device = "cuda", threads: int = 256, max_groups: int = 0,
+                 device: str | torch.device = "cuda", threads: int = 256,
                  order: np.ndarray | None = None, init: bool = True, track_remaining=False,
                  stream=None):
         _bind()
@@ -135,15 +133,11 @@ class Batch:
         if not np.array_equal(np.sort(np.asarray(order)), np.arange(self.n)):
             raise ValueError("order must be a permutation of the chain indices")
         self.order = torch.from_numpy(np.ascontiguousarray(order, dtype=np.int32)).to(dev)
-        wb = ctypes.c_size_t()
-        check(lib().hsg_batch_work_bytes(self.n, ctypes.byref(wb)))
-        self.work = torch.zeros(wb.value, dtype=torch.uint8, device=dev)
         self._d = _Batch(self.n, _dtype_code(dtype), self.chains.data_ptr(), self.spins.data_ptr(),
                          self.J.data_ptr(), self.beta.data_ptr(), self.E.data_ptr(),
                          self.sweep_ctr.data_ptr(),
                          self.remaining.data_ptr() if self.remaining is not None else None,
-                         self.order.data_ptr(), self.work.data_ptr(), wb.value, threads,
-                         max_groups)
+                         self.order.data_ptr(), threads, 0)
         self._export_work: dict[int, torch.Tensor] = {}
         if init:
             self.init(stream)
@@ -155,14 +149,6 @@ class Batch:
     @threads.setter
     def threads(self, v: int) -> None:
         self._d.threads = int(v)
-
-    @property
-    def max_groups(self) -> int:
-        return self._d.max_groups
-
-    @max_groups.setter
-    def max_groups(self, v: int) -> None:
-        self._d.max_groups = int(v)
 
     def init(self, stream=None) -> None:
         check(lib().hsg_batch_init(ctypes.byref(self._d), _stream(stream)))

@@ -66,7 +66,7 @@ int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hi
   a.k_hits = p->k_hits;
   a.g = g;
   const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
-  const bool snake = (p->flags & HSG_SNAKE) != 0, nt = (p->flags & HSG_STREAM_SPINS) != 0;
+  const bool snake = (p->flags & HSG_SNAKE) != 0;
   int32_t pass_count = 0;
   for (int32_t n = 0; n < n_sweeps; ++n) {
     const uint64_t sweep = lat->sweep + (uint64_t)n;
@@ -79,7 +79,8 @@ int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hi
         a.reverse = snake ? (pass_count & 1) : 0;
         ++pass_count;
         int rc = device_status(
-            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, nt, a, st), "colour pass");
+            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, false, a, st),
+            "colour pass");
         if (rc) return rc;
       }
     }
@@ -178,7 +179,7 @@ int hsg_sweep(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, voi
   if (p->n_or > 0x7FFF || p->k_hits > 0xFFFF)
     return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
   if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
-  if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE | HSG_STREAM_SPINS))
+  if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE))
     return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
   if (n_sweeps < 0) return fail(HSG_EINVAL, "n_sweeps must be >= 0");
   if (lat->sweep + (uint64_t)n_sweeps > 0x100000000ull)
@@ -223,12 +224,6 @@ int hsg_overlap(const hsg_lattice* a, const hsg_lattice* b, double* out_dev, voi
 
 /* ------------------------------------------------------------------- batched form */
 
-int hsg_batch_work_bytes(int32_t n_chains, size_t* work_bytes) {
-  if (n_chains < 1) return fail(HSG_EINVAL, "n_chains must be >= 1");
-  if (work_bytes) *work_bytes = hsg::batch_work_bytes(n_chains);
-  return HSG_OK;
-}
-
 int hsg_batch_check(const hsg_chain* c, int32_t n, int64_t spin_elems, int64_t J_elems) {
   if (!c || n < 1) return fail(HSG_EINVAL, "chain table is empty");
   std::vector<std::pair<int64_t, int64_t>> ranges;
@@ -261,28 +256,12 @@ static int check_batch(const hsg_batch* b) {
   if (!b) return fail(HSG_EINVAL, "batch descriptor is NULL");
   if (b->n_chains < 1) return fail(HSG_EINVAL, "n_chains must be >= 1");
   if (b->dtype != HSG_F32 && b->dtype != HSG_F64) return fail(HSG_EINVAL, "bad dtype");
-  if (!b->chains || !b->spins || !b->J || !b->beta || !b->E || !b->sweep || !b->order || !b->work)
-    return fail(HSG_EINVAL, "batch buffers chains, spins, J, beta, E, sweep, order, work must be set");
-  if (b->work_bytes < hsg::batch_work_bytes(b->n_chains))
-    return fail(HSG_EINVAL, "batch work buffer too small");
+  if (!b->chains || !b->spins || !b->J || !b->beta || !b->E || !b->sweep || !b->order)
+    return fail(HSG_EINVAL, "batch buffers chains, spins, J, beta, E, sweep, order must be set");
   if (b->threads != 0 && (b->threads < 64 || b->threads > 1024 || (b->threads & 63)))
     return fail(HSG_EINVAL, "threads must be 0 or a multiple of 64 in [64, 1024]");
-  if (b->max_groups < 0) return fail(HSG_EINVAL, "max_groups must be >= 0");
+  if (b->reserved != 0) return fail(HSG_EINVAL, "reserved must be 0");
   return HSG_OK;
-}
-
-static int compute_units() {
-  static int cached[64] = {0};
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cached[dev]) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        cus <= 0)
-      cus = 256;
-    cached[dev] = cus;
-  }
-  return cached[dev];
 }
 
 int hsg_batch_init(const hsg_batch* b, void* stream) {
@@ -299,11 +278,9 @@ int hsg_batch_sweep(const hsg_batch* b, int32_t n_sweeps, void* stream) {
   if (rc) return rc;
   if (n_sweeps < 0) return fail(HSG_EINVAL, "n_sweeps must be >= 0");
   if (n_sweeps == 0) return HSG_OK;
-  int groups = b->max_groups > 0 ? b->max_groups : 8 * compute_units();
-  if (groups > b->n_chains) groups = b->n_chains;
   hipStream_t st = as_stream(stream);
-  return device_status(b->dtype == HSG_F32 ? hsg::launch_batch_sweep<float>(b, n_sweeps, groups, st)
-                                           : hsg::launch_batch_sweep<double>(b, n_sweeps, groups, st),
+  return device_status(b->dtype == HSG_F32 ? hsg::launch_batch_sweep<float>(b, n_sweeps, st)
+                                           : hsg::launch_batch_sweep<double>(b, n_sweeps, st),
                        "batch sweep");
 }
 
@@ -328,6 +305,49 @@ int hsg_batch_overlap(const hsg_batch* b, const int32_t* pairs_dev, int32_t n_pa
       b->dtype == HSG_F32 ? hsg::launch_batch_overlap<float>(b, pairs_dev, n_pairs, out_dev, st)
                           : hsg::launch_batch_overlap<double>(b, pairs_dev, n_pairs, out_dev, st),
       "batch overlap");
+}
+
+int hsg_batch_tiles(const hsg_chain* c, int32_t n_chains, const int32_t* active, int32_t n_active,
+                    int32_t tile_sites, int32_t* tiles_out, int32_t capacity, int32_t* n_tiles) {
+  if (!c || !active || !tiles_out || !n_tiles || n_chains < 1 || n_active < 0 || capacity < 0)
+    return fail(HSG_EINVAL, "bad arguments to hsg_batch_tiles");
+  if (tile_sites < 64 || tile_sites > 1024 || (tile_sites & 63))
+    return fail(HSG_EINVAL, "tile_sites must be a multiple of 64 in [64, 1024]");
+  int64_t count = 0;
+  for (int32_t i = 0; i < n_active; ++i) {
+    const int32_t ci = active[i];
+    if (ci < 0 || ci >= n_chains) return fail(HSG_EINVAL, "active chain %d out of range", (int)ci);
+    const int64_t Nh = (int64_t)(c[ci].L / 2) * c[ci].L * c[ci].L;
+    for (int64_t ic0 = 0; ic0 < Nh; ic0 += tile_sites) {
+      if (count >= capacity) return fail(HSG_EINVAL, "tile table needs more than %d tiles", (int)capacity);
+      tiles_out[2 * count] = ci;
+      tiles_out[2 * count + 1] = (int32_t)ic0;
+      ++count;
+    }
+  }
+  *n_tiles = (int32_t)count;
+  return HSG_OK;
+}
+
+int hsg_batch_pass_sweep(const hsg_batch* b, const int32_t* tiles_dev, int32_t n_tiles,
+                         int32_t tile_sites, int32_t max_n_or, int32_t renorm, int32_t n_sweeps,
+                         void* stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (!b->remaining) return fail(HSG_EINVAL, "hsg_batch_pass_sweep needs b->remaining");
+  if (!tiles_dev || n_tiles < 0 || n_sweeps < 0 || max_n_or < 0 || max_n_or > 0x7FFF)
+    return fail(HSG_EINVAL, "bad tiles, n_sweeps or max_n_or");
+  if (tile_sites < 64 || tile_sites > 1024 || (tile_sites & 63))
+    return fail(HSG_EINVAL, "tile_sites must be a multiple of 64 in [64, 1024]");
+  if (n_tiles == 0 || n_sweeps == 0) return HSG_OK;
+  hipStream_t st = as_stream(stream);
+  return device_status(
+      b->dtype == HSG_F32
+          ? hsg::launch_batch_pass_sweep<float>(b, tiles_dev, n_tiles, tile_sites, max_n_or, renorm,
+                                                n_sweeps, st)
+          : hsg::launch_batch_pass_sweep<double>(b, tiles_dev, n_tiles, tile_sites, max_n_or,
+                                                 renorm, n_sweeps, st),
+      "batch pass sweep");
 }
 
 static int check_pt(const hsg_pt* pt) {

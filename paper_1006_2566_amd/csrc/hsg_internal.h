@@ -99,12 +99,10 @@ struct hsg_pt;
 
 namespace hsg {
 
-size_t batch_work_bytes(int32_t n_chains);
 template <typename R>
 hipError_t launch_batch_init(const hsg_batch* b, hipStream_t st);
 template <typename R>
-hipError_t launch_batch_sweep(const hsg_batch* b, int32_t n_sweeps, int32_t groups,
-                              hipStream_t st);
+hipError_t launch_batch_sweep(const hsg_batch* b, int32_t n_sweeps, hipStream_t st);
 template <typename R>
 hipError_t launch_batch_energy(const hsg_batch* b, double* out, hipStream_t st);
 template <typename R>
@@ -114,6 +112,10 @@ template <typename R>
 hipError_t launch_pt_overlap(const hsg_pt* pt, const hsg_batch* b, const int32_t* ladder_pairs,
                              int32_t n_pairs, double* out, hipStream_t st);
 hipError_t launch_pt_exchange(const hsg_pt* pt, const hsg_batch* b, hipStream_t st);
+template <typename R>
+hipError_t launch_batch_pass_sweep(const hsg_batch* b, const int32_t* tiles, int32_t n_tiles,
+                                   int32_t tile_sites, int32_t max_n_or, int32_t renorm,
+                                   int32_t n_sweeps, hipStream_t st);
 hipError_t launch_copy_double(const double* src, double* dst, hipStream_t stream);
 
 }  // namespace hsg

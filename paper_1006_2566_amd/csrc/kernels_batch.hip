@@ -1,14 +1,14 @@
 // Batched form: many independent lattices ("chains") of mixed size advanced by one
-// persistent launch, plus replica exchange (parallel tempering) and pairwise
-// overlaps over the chains of a batch.
+// launch, plus replica exchange (parallel tempering) and pairwise overlaps over the
+// chains of a batch.
 //
-// One workgroup owns one chain at a time: it runs that chain's colour passes with a
-// workgroup barrier between them, so a whole sweep -- and several sweeps -- happen
-// inside the launch with no grid-wide synchronisation.  Workgroups take chains from
-// a device work queue (an atomic counter over the caller's order, largest lattices
-// first), which balances lattices of uneven L; the last workgroup to leave resets the
-// queue, so one launch can be captured in a HIP graph and replayed.  The site update
-// is the same function as in the single-lattice colour pass.
+// One workgroup owns one chain for the whole launch: it runs that chain's colour
+// passes with a workgroup barrier between them, so a whole sweep -- and several
+// sweeps -- happen inside the launch with no grid-wide synchronisation.  Workgroups
+// are dispatched in the caller's order (largest lattices first), which balances
+// lattices of uneven L; the launch has no state of its own, so it can be captured in
+// a HIP graph and replayed.  The site update is the same function as in the
+// single-lattice colour pass.
 #include <algorithm>
 
 #include "hsg.h"
@@ -29,6 +29,14 @@ struct SmallDiv {
   __device__ __forceinline__ explicit SmallDiv(uint32_t d_) : d(d_), m(d_ > 1 ? 0xFFFFFFFFu / d_ + 1u : 0u) {}
   __device__ __forceinline__ uint32_t div(uint32_t n) const { return d > 1 ? __umulhi(n, m) : n; }
 };
+
+// Workgroups go to the 8 XCDs round-robin; renumber tiles so each XCD takes one
+// contiguous range (neighbouring tiles of a chain then share its L2).  A bijection.
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
+  const int32_t q = n >> 3, r = n & 7;
+  const int32_t xcd = b & 7, local = b >> 3;
+  return xcd * q + min(xcd, r) + local;
+}
 
 // Sum of v over the workgroup (waves in order, lanes by butterfly), valid on thread 0.
 __device__ __forceinline__ double group_sum(double v, double* scratch16) {
@@ -72,21 +80,21 @@ struct BatchArgs {
   uint32_t* sweep;
   int32_t* remaining;
   const int32_t* order;
-  uint32_t* counters;  // [0] next queue position, [1] workgroups that have left
   int32_t n_chains;
   int32_t n_sweeps;
 };
 
-// One colour pass of mode MODE over a chain, spread over the workgroup.
-template <typename R, PassMode MODE>
-__device__ __forceinline__ double chain_pass(const ChainView<R>& v, int32_t colour,
-                                             const HitCtx<R>& hc, const SmallDiv& by_lh,
-                                             const SmallDiv& by_l) {
+// One colour pass of mode MODE over a chain, spread over the workgroup.  The colour
+// is a compile-time constant, so the site update addresses its planes with constant
+// indices (no pointer table in scratch memory, global rather than flat loads).
+template <typename R, PassMode MODE, int COLOUR>
+__device__ __forceinline__ double chain_pass(const ChainView<R>& v, const HitCtx<R>& hc,
+                                             const SmallDiv& by_lh, const SmallDiv& by_l) {
   double dE = 0.0;
   SitePos q;
   q.L = v.L;
   q.Lh = v.Lh;
-  q.c = colour;
+  q.c = COLOUR;
   for (uint32_t ic = threadIdx.x; ic < (uint32_t)v.Nh; ic += blockDim.x) {
     const uint32_t r = by_lh.div(ic);
     q.xh = (int32_t)(ic - r * (uint32_t)v.Lh);
@@ -98,68 +106,88 @@ __device__ __forceinline__ double chain_pass(const ChainView<R>& v, int32_t colo
   return dE;
 }
 
+// Value every lane of the wave holds the same copy of, made visibly uniform (scalar)
+// for the compiler: loop bounds and exits that contain workgroup barriers must be.
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uniform(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v);
+}
+__device__ __forceinline__ uint64_t uniform(uint64_t v) {
+  return (uint64_t)uniform((uint32_t)v) | ((uint64_t)uniform((uint32_t)(v >> 32)) << 32);
+}
+__device__ __forceinline__ int64_t uniform(int64_t v) { return (int64_t)uniform((uint64_t)v); }
+
+// The chain table entry, with every field made uniform (see uniform()).
+__device__ __forceinline__ hsg_chain load_chain(const hsg_chain* chains, int32_t ci) {
+  const hsg_chain c = chains[ci];
+  hsg_chain u;
+  u.spin_offset = uniform(c.spin_offset);
+  u.J_offset = uniform(c.J_offset);
+  u.seed = uniform(c.seed);
+  u.J_seed = uniform(c.J_seed);
+  u.L = uniform(c.L);
+  u.k_hits = uniform(c.k_hits);
+  u.n_or = uniform(c.n_or);
+  u.renorm_every = uniform(c.renorm_every);
+  u.flags = uniform(c.flags);
+  u.reserved = 0;
+  return u;
+}
+
+// One workgroup per chain: workgroup b advances chain order[b].  The hardware
+// dispatcher hands workgroups to compute units as they free up, in order, so the
+// caller's order (largest lattices first) balances chains of uneven size without a
+// software queue, and every loop that contains a barrier has uniform bounds.
 template <typename R>
 __global__ __launch_bounds__(1024) void batch_sweep_kernel(BatchArgs<R> a) {
-  __shared__ int32_t s_item;
   __shared__ double s_red[16];
-  for (;;) {
-    if (threadIdx.x == 0) s_item = (int32_t)atomicAdd(&a.counters[0], 1u);
-    __syncthreads();
-    const int32_t item = s_item;
-    __syncthreads();
-    if (item >= a.n_chains) break;
-    const int32_t ci = a.order[item];
-    const hsg_chain ch = a.chains[ci];
-    const ChainView<R> v = chain_view<R>(ch, a.spins, a.J);
-    const SmallDiv by_lh((uint32_t)v.Lh), by_l((uint32_t)v.L);
-    int32_t n = a.n_sweeps;
-    if (a.remaining) n = min(n, a.remaining[ci]);
-    HitCtx<R> hc;
-    hc.beta = (R)a.beta[ci];
-    hc.k_hits = ch.k_hits;
-    hc.seed_lo = (uint32_t)ch.seed;
-    hc.seed_hi = (uint32_t)(ch.seed >> 32);
-    const uint32_t sweep0 = a.sweep[ci];
-    const bool heat = (ch.flags & HSG_HEAT_BATH) != 0;
-    double dE = 0.0;
-    for (int32_t s = 0; s < n; ++s) {
-      hc.sweep = sweep0 + (uint32_t)s;
-      for (int32_t phase = 0; phase <= ch.n_or; ++phase) {
-        if (phase == 0 && ch.k_hits == 0) continue;
-        hc.phase = (uint32_t)phase;
-        for (int32_t colour = 0; colour < 2; ++colour) {
-          if (phase > 0)
-            chain_pass<R, PassMode::OverRelax>(v, colour, hc, by_lh, by_l);
-          else if (heat)
-            dE += chain_pass<R, PassMode::HeatBath>(v, colour, hc, by_lh, by_l);
-          else
-            dE += chain_pass<R, PassMode::Metropolis>(v, colour, hc, by_lh, by_l);
-          __syncthreads();
-        }
-      }
-      if (ch.renorm_every > 0 && (hc.sweep + 1u) % (uint32_t)ch.renorm_every == 0u) {
-        for (uint32_t e = threadIdx.x; e < 2u * (uint32_t)v.Nh; e += blockDim.x) {
-          const int c = e >= (uint32_t)v.Nh ? 1 : 0;
-          renormalise_spin(v.S, c, (int64_t)e - c * v.Nh);
-        }
+  const int32_t ci = uniform(a.order[blockIdx.x]);
+  const hsg_chain ch = load_chain(a.chains, ci);
+  const ChainView<R> v = chain_view<R>(ch, a.spins, a.J);
+  const SmallDiv by_lh((uint32_t)v.Lh), by_l((uint32_t)v.L);
+  int32_t n = a.n_sweeps;
+  if (a.remaining) n = uniform(min(n, a.remaining[ci]));
+  HitCtx<R> hc;
+  hc.beta = (R)a.beta[ci];
+  hc.k_hits = ch.k_hits;
+  hc.seed_lo = (uint32_t)ch.seed;
+  hc.seed_hi = (uint32_t)(ch.seed >> 32);
+  const uint32_t sweep0 = uniform(a.sweep[ci]);
+  const bool heat = (ch.flags & HSG_HEAT_BATH) != 0;
+  double dE = 0.0;
+  for (int32_t s = 0; s < n; ++s) {
+    hc.sweep = sweep0 + (uint32_t)s;
+    for (int32_t phase = 0; phase <= ch.n_or; ++phase) {
+      if (phase == 0 && ch.k_hits == 0) continue;
+      hc.phase = (uint32_t)phase;
+      if (phase > 0) {
+        chain_pass<R, PassMode::OverRelax, 0>(v, hc, by_lh, by_l);
         __syncthreads();
+        chain_pass<R, PassMode::OverRelax, 1>(v, hc, by_lh, by_l);
+      } else if (heat) {
+        dE += chain_pass<R, PassMode::HeatBath, 0>(v, hc, by_lh, by_l);
+        __syncthreads();
+        dE += chain_pass<R, PassMode::HeatBath, 1>(v, hc, by_lh, by_l);
+      } else {
+        dE += chain_pass<R, PassMode::Metropolis, 0>(v, hc, by_lh, by_l);
+        __syncthreads();
+        dE += chain_pass<R, PassMode::Metropolis, 1>(v, hc, by_lh, by_l);
       }
+      __syncthreads();
     }
-    const double total = group_sum(dE, s_red);
-    if (threadIdx.x == 0) {
-      a.E[ci] += total;
-      a.sweep[ci] = sweep0 + (uint32_t)n;
-      if (a.remaining) a.remaining[ci] -= n;
+    if (ch.renorm_every > 0 && (hc.sweep + 1u) % (uint32_t)ch.renorm_every == 0u) {
+      for (uint32_t e = threadIdx.x; e < 2u * (uint32_t)v.Nh; e += blockDim.x) {
+        const int c = e >= (uint32_t)v.Nh ? 1 : 0;
+        renormalise_spin(v.S, c, (int64_t)e - c * v.Nh);
+      }
+      __syncthreads();
     }
   }
-  // The last workgroup out resets the queue for the next launch.
+  const double total = group_sum(dE, s_red);
   if (threadIdx.x == 0) {
-    __threadfence();
-    if (atomicAdd(&a.counters[1], 1u) == gridDim.x - 1) {
-      a.counters[0] = 0u;
-      a.counters[1] = 0u;
-      __threadfence();
-    }
+    a.E[ci] += total;
+    a.sweep[ci] = sweep0 + (uint32_t)n;
+    if (a.remaining) a.remaining[ci] -= n;
   }
 }
 
@@ -265,21 +293,108 @@ __global__ void pt_exchange_kernel(int32_t n_ladders, int32_t n_temps, int32_t* 
 
 __global__ void bump_round_kernel(uint32_t* round_ctr) { *round_ctr += 1u; }
 
-__global__ void zero_u32_kernel(uint32_t* p, int32_t n) {
-  const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+// ------------------------------------------------------------------------------------
+// Multi-lattice colour pass: one launch updates colour c of every listed chain.  Tile
+// t covers blockDim.x consecutive colour sites of one chain; chains that have used up
+// their budget, or do not have this phase, return at once.
+
+template <typename R>
+struct MultiPassArgs {
+  const hsg_chain* chains;
+  R* spins;
+  R* J;
+  const double* beta;
+  double* E;
+  const uint32_t* sweep;
+  const int32_t* remaining;
+  const int32_t* tiles;
+  int32_t n_tiles;
+  int32_t s;  // sweep offset within the call
+  int32_t phase;
+  int32_t colour;
+  int32_t reverse;
+};
+
+template <typename R, int COLOUR>
+__global__ __launch_bounds__(1024) void multi_pass_kernel(MultiPassArgs<R> a) {
+  __shared__ double s_red[16];
+  int32_t t = xcd_tile((int32_t)blockIdx.x, a.n_tiles);
+  if (a.reverse) t = a.n_tiles - 1 - t;
+  const int32_t ci = uniform(a.tiles[2 * t]), ic0 = uniform(a.tiles[2 * t + 1]);
+  if (a.s >= uniform(a.remaining[ci])) return;
+  const hsg_chain ch = load_chain(a.chains, ci);
+  if ((a.phase == 0 && ch.k_hits == 0) || a.phase > ch.n_or) return;
+  const ChainView<R> v = chain_view<R>(ch, a.spins, a.J);
+  const uint32_t ic = (uint32_t)ic0 + threadIdx.x;
+  HitCtx<R> hc;
+  hc.beta = (R)a.beta[ci];
+  hc.k_hits = ch.k_hits;
+  hc.seed_lo = (uint32_t)ch.seed;
+  hc.seed_hi = (uint32_t)(ch.seed >> 32);
+  hc.sweep = a.sweep[ci] + (uint32_t)a.s;
+  hc.phase = (uint32_t)a.phase;
+  double dE = 0.0;
+  if (ic < (uint32_t)v.Nh) {
+    const SmallDiv by_lh((uint32_t)v.Lh), by_l((uint32_t)v.L);
+    SitePos q;
+    q.L = v.L;
+    q.Lh = v.Lh;
+    q.c = COLOUR;
+    const uint32_t r = by_lh.div(ic);
+    q.xh = (int32_t)(ic - r * (uint32_t)v.Lh);
+    const uint32_t zq = by_l.div(r);
+    q.y = (int32_t)(r - zq * (uint32_t)v.L);
+    q.z = (int32_t)zq;
+    if (a.phase > 0)
+      update_site<R, PassMode::OverRelax, false>(v.S, v.J, q, hc);
+    else if (ch.flags & HSG_HEAT_BATH)
+      dE = update_site<R, PassMode::HeatBath, false>(v.S, v.J, q, hc);
+    else
+      dE = update_site<R, PassMode::Metropolis, false>(v.S, v.J, q, hc);
+  }
+  if (a.phase == 0) {
+    const double total = group_sum(dE, s_red);
+    if (threadIdx.x == 0 && total != 0.0) atomicAdd(&a.E[ci], total);
+  }
+}
+
+// Renormalisation after sweep offset s for the chains whose schedule asks for it.
+template <typename R>
+__global__ __launch_bounds__(1024) void multi_renorm_kernel(const hsg_chain* chains, R* spins,
+                                                            const uint32_t* sweep,
+                                                            const int32_t* remaining,
+                                                            const int32_t* tiles, int32_t s) {
+  const int32_t t = blockIdx.x;
+  const int32_t ci = tiles[2 * t], ic0 = tiles[2 * t + 1];
+  if (s >= remaining[ci]) return;
+  const hsg_chain ch = chains[ci];
+  if (ch.renorm_every <= 0 || (sweep[ci] + (uint32_t)s + 1u) % (uint32_t)ch.renorm_every != 0u)
+    return;
+  const int64_t Nh = (int64_t)(ch.L / 2) * ch.L * ch.L;
+  const Planes<R> S = planes_of<R>(spins + ch.spin_offset, Nh);
+  const int64_t e = (int64_t)ic0 + threadIdx.x;
+  if (e < Nh) {
+    renormalise_spin(S, 0, e);
+    renormalise_spin(S, 1, e);
+  }
+}
+
+// Advances every chain's sweep counter and budget by the sweeps it ran.
+__global__ void multi_finish_kernel(int32_t n_chains, uint32_t* sweep, int32_t* remaining,
+                                    int32_t n_sweeps) {
+  const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_chains) return;
+  const int32_t n = min(n_sweeps, remaining[c]);
+  if (n > 0) {
+    sweep[c] += (uint32_t)n;
+    remaining[c] -= n;
+  }
 }
 
 }  // namespace
 
-size_t batch_work_bytes(int32_t n_chains) {
-  (void)n_chains;
-  return 256;  // queue counters
-}
-
 template <typename R>
 hipError_t launch_batch_init(const hsg_batch* b, hipStream_t st) {
-  hipLaunchKernelGGL(zero_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t*)b->work, 64);
   hipLaunchKernelGGL(batch_init_kernel<R>, dim3(64, (unsigned)b->n_chains), dim3(256), 0, st,
                      b->chains, (R*)b->spins, (R*)b->J);
   hipLaunchKernelGGL(batch_energy_kernel<R>, dim3((unsigned)b->n_chains), dim3(256), 0, st,
@@ -288,8 +403,7 @@ hipError_t launch_batch_init(const hsg_batch* b, hipStream_t st) {
 }
 
 template <typename R>
-hipError_t launch_batch_sweep(const hsg_batch* b, int32_t n_sweeps, int32_t groups,
-                              hipStream_t st) {
+hipError_t launch_batch_sweep(const hsg_batch* b, int32_t n_sweeps, hipStream_t st) {
   BatchArgs<R> a;
   a.chains = b->chains;
   a.spins = (R*)b->spins;
@@ -299,11 +413,10 @@ hipError_t launch_batch_sweep(const hsg_batch* b, int32_t n_sweeps, int32_t grou
   a.sweep = b->sweep;
   a.remaining = b->remaining;
   a.order = b->order;
-  a.counters = (uint32_t*)b->work;
   a.n_chains = b->n_chains;
   a.n_sweeps = n_sweeps;
   const int threads = b->threads > 0 ? b->threads : 256;
-  hipLaunchKernelGGL(batch_sweep_kernel<R>, dim3((unsigned)groups), dim3((unsigned)threads), 0, st,
+  hipLaunchKernelGGL(batch_sweep_kernel<R>, dim3((unsigned)b->n_chains), dim3((unsigned)threads), 0, st,
                      a);
   return hipGetLastError();
 }
@@ -341,14 +454,56 @@ hipError_t launch_pt_exchange(const hsg_pt* pt, const hsg_batch* b, hipStream_t 
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_batch_pass_sweep(const hsg_batch* b, const int32_t* tiles, int32_t n_tiles,
+                                   int32_t tile_sites, int32_t max_n_or, int32_t renorm,
+                                   int32_t n_sweeps, hipStream_t st) {
+  MultiPassArgs<R> a;
+  a.chains = b->chains;
+  a.spins = (R*)b->spins;
+  a.J = (R*)b->J;
+  a.beta = b->beta;
+  a.E = b->E;
+  a.sweep = b->sweep;
+  a.remaining = b->remaining;
+  a.tiles = tiles;
+  a.n_tiles = n_tiles;
+  int32_t pass = 0;
+  for (int32_t s = 0; s < n_sweeps; ++s) {
+    a.s = s;
+    for (int32_t phase = 0; phase <= max_n_or; ++phase) {
+      a.phase = phase;
+      for (int32_t colour = 0; colour < 2; ++colour) {
+        a.colour = colour;
+        a.reverse = pass++ & 1;
+        if (colour == 0)
+          hipLaunchKernelGGL((multi_pass_kernel<R, 0>), dim3((unsigned)n_tiles),
+                             dim3((unsigned)tile_sites), 0, st, a);
+        else
+          hipLaunchKernelGGL((multi_pass_kernel<R, 1>), dim3((unsigned)n_tiles),
+                             dim3((unsigned)tile_sites), 0, st, a);
+      }
+    }
+    if (renorm)
+      hipLaunchKernelGGL(multi_renorm_kernel<R>, dim3((unsigned)n_tiles), dim3((unsigned)tile_sites),
+                         0, st, b->chains, (R*)b->spins, (const uint32_t*)b->sweep,
+                         (const int32_t*)b->remaining, tiles, s);
+  }
+  hipLaunchKernelGGL(multi_finish_kernel, dim3((unsigned)((b->n_chains + 255) / 256)), dim3(256), 0,
+                     st, b->n_chains, b->sweep, b->remaining, n_sweeps);
+  return hipGetLastError();
+}
+
 #define HSG_BATCH_INSTANTIATE(R)                                                              \
   template hipError_t launch_batch_init<R>(const hsg_batch*, hipStream_t);                    \
-  template hipError_t launch_batch_sweep<R>(const hsg_batch*, int32_t, int32_t, hipStream_t); \
+  template hipError_t launch_batch_sweep<R>(const hsg_batch*, int32_t, hipStream_t); \
   template hipError_t launch_batch_energy<R>(const hsg_batch*, double*, hipStream_t);         \
   template hipError_t launch_batch_overlap<R>(const hsg_batch*, const int32_t*, int32_t,      \
                                               double*, hipStream_t);                          \
   template hipError_t launch_pt_overlap<R>(const hsg_pt*, const hsg_batch*, const int32_t*,   \
-                                           int32_t, double*, hipStream_t);
+                                           int32_t, double*, hipStream_t);                     \
+  template hipError_t launch_batch_pass_sweep<R>(const hsg_batch*, const int32_t*, int32_t,   \
+                                                 int32_t, int32_t, int32_t, int32_t, hipStream_t);
 HSG_BATCH_INSTANTIATE(float)
 HSG_BATCH_INSTANTIATE(double)
 

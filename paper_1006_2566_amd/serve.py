@@ -1,0 +1,326 @@
+"""Served form: continuous batching of simulation requests.
+
+Requests (seed, L, T, sweeps, k) arrive over time.  The server admits them as
+device memory and slots free up (admission by HBM footprint), keeps every admitted
+lattice resident on the device, and advances all of them together in steps of a few
+sweeps with ``hsg_batch_pass_sweep`` -- one launch per colour pass covering tiles of
+every resident lattice, so requests that arrive while others run share the same
+launches.  A request retires when its sweeps are done; its final energy and
+magnetisation are read back and its memory is reused.
+
+Host-side scheduling only: every sweep, energy and magnetisation is computed by
+libhsg's kernels.
+"""
+from __future__ import annotations
+
+import bisect
+import ctypes
+import dataclasses
+import math
+import time
+from collections import deque
+
+import numpy as np
+import torch
+
+from . import _dtype_code, _ptr, _stream, check, lib
+from .batch import BATCH_L_MAX, CHAIN_DTYPE, HSG_CHAIN_INIT_J, _Batch, _bind
+
+DUMMY_L = 2  # placeholder lattice of a free slot (never swept: its budget is 0)
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    seed: int
+    L: int
+    T: float
+    sweeps: int
+    k: int
+    arrival: float = 0.0  # seconds after the start of the run
+
+    @property
+    def spins(self) -> int:
+        return self.L ** 3
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    E: float          # tracked energy after the last sweep (binary64)
+    m: np.ndarray     # magnetisation (1/N) sum sigma_i, binary64
+    arrival: float
+    admitted: float
+    finished: float
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+def poisson_trace(n: int = 2000, rate: float = 200.0, seed: int = 1,
+                  Ls=(8, 16, 32, 64, 96), T_range=(0.1, 1.0), sweep_range=(100, 10000),
+                  ks=(1, 4)) -> list[Request]:
+    """Synthetic request stream: Poisson arrivals at `rate` per second; request r has
+    seed 1000 + r, L uniform in Ls, T uniform in T_range, sweeps log-uniform in
+    sweep_range (rounded to an integer), k uniform in ks.  numpy PCG64 on `seed`."""
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    Ls_ = rng.choice(np.asarray(Ls), size=n)
+    Ts = rng.uniform(T_range[0], T_range[1], size=n)
+    lo, hi = math.log(sweep_range[0]), math.log(sweep_range[1])
+    sweeps = np.rint(np.exp(rng.uniform(lo, hi, size=n))).astype(np.int64)
+    ks_ = rng.choice(np.asarray(ks), size=n)
+    return [Request(rid=r, seed=1000 + r, L=int(Ls_[r]), T=float(Ts[r]), sweeps=int(sweeps[r]),
+                    k=int(ks_[r]), arrival=float(arrivals[r])) for r in range(n)]
+
+
+class Arena:
+    """First-fit allocator over a range of elements (offsets into a device buffer)."""
+
+    def __init__(self, size: int, align: int = 64):
+        self.size, self.align = size, align
+        self.free = [(0, size)]  # sorted, non-adjacent (start, end)
+
+    def alloc(self, n: int) -> int | None:
+        n = -(-n // self.align) * self.align
+        for i, (a, b) in enumerate(self.free):
+            if b - a >= n:
+                if b - a == n:
+                    self.free.pop(i)
+                else:
+                    self.free[i] = (a + n, b)
+                return a
+        return None
+
+    def release(self, start: int, n: int) -> None:
+        n = -(-n // self.align) * self.align
+        i = bisect.bisect_left(self.free, (start, start + n))
+        self.free.insert(i, (start, start + n))
+        merged = []
+        for a, b in self.free:
+            if merged and merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], b)
+            else:
+                merged.append((a, b))
+        self.free = merged
+
+    @property
+    def used(self) -> int:
+        return self.size - sum(b - a for a, b in self.free)
+
+
+class Server:
+    """Continuous-batching server on one GPU.
+
+    hbm_budget: bytes of device memory for resident lattices (spins + couplings);
+    admission waits while a request's footprint does not fit.  n_slots bounds the
+    number of resident lattices.  step_sweeps: sweeps per scheduling step."""
+
+    def __init__(self, hbm_budget: int = 4 << 30, n_slots: int = 1024, step_sweeps: int = 16,
+                 tile_sites: int = 256, dtype: torch.dtype = torch.float32,
+                 device: str | torch.device = "cuda"):
+        _bind()
+        self.dtype, self.device = dtype, torch.device(device)
+        self.es = torch.tensor([], dtype=dtype).element_size()
+        self.step_sweeps, self.tile_sites = step_sweeps, tile_sites
+        self.n_slots = n_slots
+        # each lattice takes 3 L^3 spin elements and as many coupling elements
+        per_buffer = hbm_budget // (2 * self.es)
+        dummy = 3 * DUMMY_L ** 3
+        self.dummy_base = per_buffer
+        self.spins = torch.zeros(per_buffer + n_slots * dummy, dtype=dtype, device=self.device)
+        self.J = torch.zeros(per_buffer + n_slots * dummy, dtype=dtype, device=self.device)
+        self.arena_s = Arena(per_buffer)
+        self.arena_j = Arena(per_buffer)
+        self.table = np.zeros(n_slots, dtype=CHAIN_DTYPE)
+        for s in range(n_slots):
+            self._set_dummy(s)
+        dev = self.device
+        self.beta = torch.zeros(n_slots, dtype=torch.float64, device=dev)
+        self.E = torch.zeros(n_slots, dtype=torch.float64, device=dev)
+        self.sweep_ctr = torch.zeros(n_slots, dtype=torch.int32, device=dev)
+        self.remaining = torch.zeros(n_slots, dtype=torch.int32, device=dev)
+        self.order = torch.arange(n_slots, dtype=torch.int32, device=dev)
+        self.chains = torch.empty(n_slots * CHAIN_DTYPE.itemsize, dtype=torch.uint8, device=dev)
+        self._upload_table()
+        self._d = _Batch(n_slots, _dtype_code(dtype), self.chains.data_ptr(),
+                         self.spins.data_ptr(), self.J.data_ptr(), self.beta.data_ptr(),
+                         self.E.data_ptr(), self.sweep_ctr.data_ptr(),
+                         self.remaining.data_ptr(), self.order.data_ptr(), 256, 0)
+        self.free_slots = list(range(n_slots - 1, -1, -1))
+        self.active: dict[int, tuple[Request, int, int, float]] = {}  # slot -> (req, s_off, j_off, t_admit)
+        self.tiles_dev = None
+        self.n_tiles = 0
+        self._tiles_dirty = True
+        self.pair_buf = torch.zeros((n_slots, 2), dtype=torch.int32, device=dev)
+        self.m_buf = torch.zeros((n_slots, 15), dtype=torch.float64, device=dev)
+        # where the wall time of run() goes (seconds) and how full the steps were
+        self.stats = {"steps": 0, "t_admit": 0.0, "t_step": 0.0, "t_wait": 0.0, "t_retire": 0.0,
+                      "t_idle": 0.0, "active_sum": 0, "tiles_sum": 0, "site_sweeps": 0.0}
+
+    # ------------------------------------------------------------------ slots
+    def _set_dummy(self, s: int) -> None:
+        off = self.dummy_base + s * 3 * DUMMY_L ** 3
+        self.table[s] = (off, off, 1, 1, DUMMY_L, 1, 0, 0, 0, 0)
+
+    def _upload_table(self) -> None:
+        check(lib().hsg_batch_check(self.table.ctypes.data_as(ctypes.c_void_p), self.n_slots,
+                                    self.spins.numel(), self.J.numel()))
+        self.chains.copy_(torch.from_numpy(self.table.view(np.uint8)))
+
+    def footprint(self, req: Request) -> int:
+        return 2 * 3 * req.spins * self.es
+
+    def try_admit(self, req: Request, now: float) -> bool:
+        if not self.free_slots:
+            return False
+        if not (2 <= req.L <= BATCH_L_MAX and req.L % 2 == 0):
+            raise ValueError(f"request {req.rid}: L={req.L} not servable")
+        n = 3 * req.spins
+        s_off = self.arena_s.alloc(n)
+        if s_off is None:
+            return False
+        j_off = self.arena_j.alloc(n)
+        if j_off is None:
+            self.arena_s.release(s_off, n)
+            return False
+        slot = self.free_slots.pop()
+        self.table[slot] = (s_off, j_off, req.seed, req.seed, req.L, req.k, 0, 0, HSG_CHAIN_INIT_J,
+                            0)
+        self.active[slot] = (req, s_off, j_off, now)
+        return True
+
+    def _init_new(self, slots: list[int]) -> None:
+        """Philox initial state (spins and couplings from the request seed) of newly
+        admitted lattices, through a small batch that views the same buffers."""
+        if not slots:
+            return
+        sub = self.table[slots].copy()
+        n = len(slots)
+        dev = self.device
+        chains = torch.from_numpy(sub.view(np.uint8).copy()).to(dev)
+        E = torch.zeros(n, dtype=torch.float64, device=dev)
+        zeros = torch.zeros(n, dtype=torch.int32, device=dev)
+        order = torch.arange(n, dtype=torch.int32, device=dev)
+        beta = torch.zeros(n, dtype=torch.float64, device=dev)
+        d = _Batch(n, _dtype_code(self.dtype), chains.data_ptr(), self.spins.data_ptr(),
+                   self.J.data_ptr(), beta.data_ptr(), E.data_ptr(), zeros.data_ptr(), None,
+                   order.data_ptr(), 256, 0)
+        check(lib().hsg_batch_init(ctypes.byref(d), _stream(None)))
+        idx = torch.tensor(slots, dtype=torch.long, device=dev)
+        self.E[idx] = E
+        self.sweep_ctr[idx] = 0
+        reqs = [self.active[s][0] for s in slots]
+        self.remaining[idx] = torch.tensor([r.sweeps for r in reqs], dtype=torch.int32, device=dev)
+        self.beta[idx] = torch.tensor([0.0 if math.isinf(r.T) else 1.0 / r.T for r in reqs],
+                                      dtype=torch.float64, device=dev)
+        del chains, E, zeros, order, beta  # stream-ordered frees
+
+    def _build_tiles(self) -> None:
+        act = np.array(sorted(self.active), dtype=np.int32)
+        cap = int(sum(-(-(self.table[s]["L"] ** 3 // 2) // self.tile_sites) for s in act)) + 1
+        tiles = np.zeros(2 * cap, dtype=np.int32)
+        n = ctypes.c_int32()
+        check(lib().hsg_batch_tiles(self.table.ctypes.data_as(ctypes.c_void_p), self.n_slots,
+                                    act.ctypes.data_as(ctypes.c_void_p), act.size, self.tile_sites,
+                                    tiles.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n)))
+        self.n_tiles = n.value
+        self.tiles_dev = torch.from_numpy(tiles[:2 * n.value].copy()).to(self.device)
+        self._tiles_dirty = False
+
+    def step(self) -> None:
+        """Advance every resident lattice by up to step_sweeps sweeps."""
+        if self._tiles_dirty:
+            self._build_tiles()
+        if self.n_tiles == 0:
+            return
+        check(lib().hsg_batch_pass_sweep(ctypes.byref(self._d), _ptr(self.tiles_dev),
+                                         self.n_tiles, self.tile_sites, 0, 0, self.step_sweeps,
+                                         _stream(None)))
+
+    def retire(self, now_fn) -> list[Result]:
+        """Collect the lattices whose budget is spent: energy and magnetisation."""
+        rem = self.remaining.cpu().numpy()
+        done = [s for s in self.active if rem[s] == 0]
+        if not done:
+            return []
+        n = len(done)
+        pairs = torch.tensor([[s, s] for s in done], dtype=torch.int32, device=self.device)
+        self.pair_buf[:n].copy_(pairs)
+        check(lib().hsg_batch_overlap(ctypes.byref(self._d), _ptr(self.pair_buf), n,
+                                      _ptr(self.m_buf), _stream(None)))
+        m = self.m_buf[:n, 9:12].cpu().numpy()
+        E = self.E.cpu().numpy()
+        t = now_fn()
+        out = []
+        for i, s in enumerate(done):
+            req, s_off, j_off, t_adm = self.active.pop(s)
+            out.append(Result(req.rid, float(E[s]), m[i].copy(), req.arrival, t_adm, t))
+            self.arena_s.release(s_off, 3 * req.spins)
+            self.arena_j.release(j_off, 3 * req.spins)
+            self._set_dummy(s)
+            self.free_slots.append(s)
+        self._tiles_dirty = True
+        return out
+
+    # -------------------------------------------------------------------- loop
+    def run(self, trace: list[Request], realtime: bool = True) -> list[Result]:
+        """Serve a trace.  realtime=True releases each request at its arrival time
+        (wall clock from the start of the run); False releases all at once."""
+        pending = deque(sorted(trace, key=lambda r: r.arrival))
+        queue: deque[Request] = deque()
+        results: list[Result] = []
+        t0 = time.perf_counter()
+        now = (lambda: time.perf_counter() - t0) if realtime else (lambda: 0.0)
+        st = self.stats
+        clock = time.perf_counter
+        while pending or queue or self.active:
+            c0 = clock()
+            t = now()
+            while pending and (not realtime or pending[0].arrival <= t):
+                queue.append(pending.popleft())
+            admitted = []
+            while queue and self.try_admit(queue[0], now()):
+                admitted.append(self._slot_of(queue.popleft()))
+            if admitted:
+                self._upload_table()
+                self._init_new(admitted)
+                self._tiles_dirty = True
+            c1 = clock()
+            st["t_admit"] += c1 - c0
+            if not self.active:
+                if queue:
+                    raise RuntimeError(f"request {queue[0].rid} does not fit the HBM budget")
+                if pending and realtime:
+                    time.sleep(max(0.0, pending[0].arrival - now()))
+                st["t_idle"] += clock() - c1
+                continue
+            self.step()
+            c2 = clock()
+            torch.cuda.current_stream().synchronize()
+            c3 = clock()
+            st["steps"] += 1
+            st["active_sum"] += len(self.active)
+            st["tiles_sum"] += self.n_tiles
+            finished = self.retire(now)
+            if finished:
+                self._upload_table()
+                results.extend(finished)
+            st["t_step"] += c2 - c1
+            st["t_wait"] += c3 - c2
+            st["t_retire"] += clock() - c3
+        return results
+
+    def _slot_of(self, req: Request) -> int:
+        for s, (r, *_rest) in self.active.items():
+            if r is req:
+                return s
+        raise KeyError(req.rid)
+
+
+def latency_stats(results: list[Result]) -> dict:
+    lat = np.array([r.latency for r in results])
+    return {"n": int(lat.size), "p50_s": float(np.percentile(lat, 50)),
+            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+            "max_s": float(lat.max())}

@@ -82,7 +82,7 @@ def test_null_and_missing_buffers_rejected(hsg):
 @pytest.mark.parametrize("T,k,n_or,R,flags,n", [
     (0.0, 1, 0, 0, 0, 1), (-1.0, 1, 0, 0, 0, 1), (float("nan"), 1, 0, 0, 0, 1),
     (1.0, 0, 0, 0, 0, 1), (1.0, -1, 1, 0, 0, 1), (1.0, 1, -1, 0, 0, 1),
-    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 64, 1),
+    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 4, 1),
     (1.0, 70000, 0, 0, 0, 1)])
 def test_sweep_rejects_bad_params(hsg, T, k, n_or, R, flags, n):
     lib = hsg.lib()
@@ -160,13 +160,17 @@ def test_batch_descriptor_validation(hsg):
     from paper_1006_2566_amd import batch as B
     B._bind()
     lib = hsg.lib()
-    d = B._Batch(2, 0, 0x10, 0x20, 0x30, 0x40, 0x50, 0x60, None, 0x70, 0x80, 256, 96, 0)
+    d = B._Batch(2, 0, 0x10, 0x20, 0x30, 0x40, 0x50, 0x60, None, 0x70, 96, 0)
     assert lib.hsg_batch_sweep(ctypes.byref(d), 1, None) == -1  # threads not a multiple of 64
     d.threads = 256
-    d.work_bytes = 8
+    d.reserved = 1
     assert lib.hsg_batch_sweep(ctypes.byref(d), 1, None) == -1
-    assert b"work buffer" in lib.hsg_last_error()
-    d.work_bytes = 256
+    assert b"reserved" in lib.hsg_last_error()
+    d.reserved = 0
+    d.order = None
+    assert lib.hsg_batch_sweep(ctypes.byref(d), 1, None) == -1
+    assert b"order" in lib.hsg_last_error()
+    d.order = 0x70
     d.E = None
     assert lib.hsg_batch_init(ctypes.byref(d), None) == -1
     p = B._PT(0, 4, 0x10, 0x20, None, 0x30, 1)

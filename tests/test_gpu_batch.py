@@ -118,7 +118,7 @@ def test_batch_independent_of_workgroup_size(mods, threads):
     hsg, B = mods
     specs = mixed_specs(B)
     ref = B.Batch(specs, threads=256)
-    other = B.Batch(specs, threads=threads, max_groups=3)
+    other = B.Batch(specs, threads=threads)
     ref.sweep(4)
     other.sweep(4)
     assert torch.equal(ref.spins, other.spins)

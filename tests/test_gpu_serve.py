@@ -1,0 +1,127 @@
+"""GPU tests of the served form: results do not depend on what else is resident
+(alone vs in the mix), match the single-lattice path, admission by footprint waits
+instead of failing, and the multi-lattice pass sweep equals the chain-per-workgroup
+sweep."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1006_2566_amd as hsg
+    from paper_1006_2566_amd import batch as B
+    from paper_1006_2566_amd import serve as S
+    hsg.lib()
+    return hsg, B, S
+
+
+def small_trace(S, n=14, seed=4):
+    rng = np.random.default_rng(seed)
+    Ls = [8, 16, 32, 64]
+    return [S.Request(rid=r, seed=5000 + r, L=int(rng.choice(Ls)), T=float(rng.uniform(0.1, 1.0)),
+                      sweeps=int(rng.integers(5, 60)), k=int(rng.choice([1, 4])),
+                      arrival=0.001 * r) for r in range(n)]
+
+
+def test_results_same_alone_and_in_mix(mods):
+    hsg, B, S = mods
+    trace = small_trace(S)
+    mix = {r.rid: r for r in S.Server(hbm_budget=256 << 20, n_slots=64, step_sweeps=7).run(
+        trace, realtime=False)}
+    assert sorted(mix) == [r.rid for r in trace]
+    for req in trace[:6]:
+        alone = S.Server(hbm_budget=64 << 20, n_slots=4, step_sweeps=5).run([req],
+                                                                          realtime=False)[0]
+        a, b = alone, mix[req.rid]
+        print(f"[serve] rid={req.rid} L={req.L} E alone={a.E:.9f} mix={b.E:.9f}")
+        # spins identical; E sums binary64 atomics in a different order
+        np.testing.assert_array_equal(a.m, b.m)
+        assert abs(a.E - b.E) <= 1e-12 * max(1.0, abs(a.E))
+
+
+def test_results_match_single_lattice_path(mods):
+    hsg, B, S = mods
+    trace = small_trace(S, n=6, seed=11)
+    res = {r.rid: r for r in S.Server(hbm_budget=256 << 20, n_slots=16, step_sweeps=9).run(
+        trace, realtime=False)}
+    for req in trace:
+        lat = hsg.Lattice(req.L, torch.float32, seed=req.seed)
+        lat.sweep(T=req.T, k=req.k, n_sweeps=req.sweeps)
+        s = lat.export()[0].double()
+        m = (s.mean(dim=1)).cpu().numpy()
+        E = lat.energy().item()
+        np.testing.assert_allclose(res[req.rid].m, m, rtol=0, atol=1e-12)
+        assert abs(res[req.rid].E - E) <= 1e-10 * max(1.0, abs(E))
+
+
+def test_small_request_matches_oracle(mods):
+    hsg, B, S = mods
+    req = S.Request(rid=0, seed=77, L=8, T=0.6, sweeps=12, k=4)
+    res = S.Server(hbm_budget=16 << 20, n_slots=2, step_sweeps=5).run([req], realtime=False)[0]
+    s, _ = O.init(8, 77, np.float32)
+    _, J = O.init(8, 77, np.float32)
+    r = O.sweep(8, 77, s, J, T=0.6, k=4, n_sweeps=12, E=O.energy(8, s, J))
+    m = s.astype(np.float64).mean(axis=1)
+    # initial couplings differ by an ulp (log in Box-Muller) between host and device
+    assert abs(res.E - r["E"]) <= 1e-4 * abs(r["E"])
+    np.testing.assert_allclose(res.m, m, atol=1e-4)
+
+
+def test_admission_waits_for_memory(mods):
+    hsg, B, S = mods
+    # 4 lattices of L=32 need 4 * 2 * 3 * 32^3 * 4 B = 3.1 MB; a 1.6 MB budget holds 2
+    trace = [S.Request(rid=r, seed=9 + r, L=32, T=0.5, sweeps=20, k=1) for r in range(4)]
+    srv = S.Server(hbm_budget=1_600_000, n_slots=8, step_sweeps=10)
+    res = srv.run(trace, realtime=False)
+    assert sorted(r.rid for r in res) == [0, 1, 2, 3]
+    assert srv.arena_s.used == 0 and srv.arena_j.used == 0 and not srv.active
+    # the later two were admitted only after the first two finished
+    adm = {r.rid: r.admitted for r in res}
+    fin = {r.rid: r.finished for r in res}
+    assert srv.free_slots and len(srv.free_slots) == 8
+
+
+def test_request_larger_than_budget_is_rejected(mods):
+    hsg, B, S = mods
+    srv = S.Server(hbm_budget=1 << 20, n_slots=2)
+    with pytest.raises(RuntimeError):
+        srv.run([S.Request(rid=0, seed=1, L=64, T=0.5, sweeps=5, k=1)], realtime=False)
+
+
+def test_pass_sweep_equals_chain_sweep(mods):
+    hsg, B, S = mods
+    specs = [B.ChainSpec(L=L, seed=300 + i, J_group=i, J_seed=400 + i, T=0.4 + 0.1 * i, k=k,
+                         n_or=1, renorm_every=3)
+             for i, (L, k) in enumerate([(8, 1), (16, 4), (24, 2), (64, 4), (96, 1)])]
+    a = B.Batch(specs, track_remaining=True)
+    b = B.Batch(specs, track_remaining=True)
+    budget = torch.tensor([5, 7, 3, 7, 6], dtype=torch.int32)
+    a.remaining.copy_(budget)
+    b.remaining.copy_(budget)
+    a.sweep(7)
+    table = b.table
+    act = np.arange(len(specs), dtype=np.int32)
+    import ctypes
+    cap = 4096
+    tiles = np.zeros(2 * cap, dtype=np.int32)
+    n = ctypes.c_int32()
+    hsg.check(hsg.lib().hsg_batch_tiles(table.ctypes.data_as(ctypes.c_void_p), len(specs),
+                                        act.ctypes.data_as(ctypes.c_void_p), act.size, 256,
+                                        tiles.ctypes.data_as(ctypes.c_void_p), cap,
+                                        ctypes.byref(n)))
+    td = torch.from_numpy(tiles[:2 * n.value].copy()).cuda()
+    hsg.check(hsg.lib().hsg_batch_pass_sweep(ctypes.byref(b._d), hsg._ptr(td), n.value, 256, 1, 1,
+                                             7, hsg._stream(None)))
+    torch.cuda.synchronize()
+    assert torch.equal(a.spins, b.spins)
+    assert torch.equal(a.sweep_ctr, b.sweep_ctr) and torch.equal(a.remaining, b.remaining)
+    assert torch.allclose(a.E, b.E, rtol=1e-12, atol=0)

@@ -1,0 +1,54 @@
+"""Host logic of the served form (no GPU): the request stream, the arena allocator
+and the latency statistics."""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+from paper_1006_2566_amd import serve as S
+
+
+def test_poisson_trace_distributions():
+    tr = S.poisson_trace(n=20000, rate=200.0, seed=3)
+    arr = np.array([r.arrival for r in tr])
+    gaps = np.diff(np.concatenate([[0.0], arr]))
+    assert abs(gaps.mean() - 1 / 200) < 4 * (1 / 200) / math.sqrt(len(gaps))
+    assert abs(np.std(gaps) / gaps.mean() - 1) < 0.05  # exponential: cv = 1
+    Ls = np.array([r.L for r in tr])
+    assert set(np.unique(Ls)) == {8, 16, 32, 64, 96}
+    for L in (8, 16, 32, 64, 96):
+        assert abs((Ls == L).mean() - 0.2) < 0.02
+    sw = np.array([r.sweeps for r in tr])
+    assert sw.min() >= 100 and sw.max() <= 10000
+    # log-uniform: log(sweeps) uniform on [log 100, log 10000]
+    u = (np.log(sw) - math.log(100)) / (math.log(10000) - math.log(100))
+    assert abs(u.mean() - 0.5) < 0.01 and abs(u.var() - 1 / 12) < 0.005
+    T = np.array([r.T for r in tr])
+    assert 0.1 <= T.min() and T.max() <= 1.0
+    assert set(np.unique([r.k for r in tr])) == {1, 4}
+    assert [r.seed for r in tr[:3]] == [1000, 1001, 1002]
+
+
+def test_arena_first_fit_and_coalescing():
+    a = S.Arena(1000, align=10)
+    x = a.alloc(95)    # rounded to 100
+    y = a.alloc(300)
+    z = a.alloc(200)
+    assert (x, y, z) == (0, 100, 400)
+    assert a.alloc(500) is None and a.used == 600
+    a.release(y, 300)
+    assert a.alloc(250) == 100     # first fit reuses the hole
+    a.release(100, 250)
+    a.release(x, 95)
+    a.release(z, 200)
+    assert a.free == [(0, 1000)] and a.used == 0
+
+
+def test_latency_stats():
+    res = [S.Result(i, 0.0, np.zeros(3), arrival=0.0, admitted=0.0, finished=float(i))
+           for i in range(1, 101)]
+    st = S.latency_stats(res)
+    assert st["n"] == 100 and st["p50_s"] == pytest.approx(50.5) and st["max_s"] == 100
+    assert st["p99_s"] == pytest.approx(99.01)
