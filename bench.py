@@ -22,8 +22,28 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "spin updates/ns at L=256 FP32 (k=1,4,8) + %HBM roofline; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BYTES_PER_SITE_PHASE = 36.0  # binary32: read spin (12) + 3 bonds (12), write spin (12)
+# 32-bit vector ALU peak of MI355X: the 157.3 TFLOP/s binary32 vector figure counts a
+# fused multiply-add as 2 flops, so 78.6e12 lane operations per second (256 compute
+# units x 128 lanes x 2.4 GHz).
+ALU_PEAK_TOPS = 157.3 / 2
+# Algorithmic 32-bit lane operations of the Metropolis pass (a fused multiply-add, a
+# compare, a select, each half of a 32x32->64 product counts one):
+#   per site: local field 3 x (1 mul + 5 fma) = 18, sigma.h 3          -> 21
+#   per hit:  Philox4x32-10 10 rounds x (2 products x 2 halves + 4 xor) = 80
+#             three uniforms 3 x (shift, or, convert, scale)            = 12
+#             trial point: 2u-1, 1-z^2, sqrt, 4u, rint, r, r^2, sin (5), cos (5),
+#             quadrant (convert, and, 4 selects), rho cos, rho sin      = 25
+#             decision: s.h (3), dE, -beta dE, exp (2), dE <= 0, u < p, or,
+#             4 selects (spin, s.h), energy sum (convert, add)          = 16
+OPS_PER_SITE = 21
+OPS_PER_HIT = 80 + 12 + 25 + 16
+KERNEL_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/csrc/hsg_device.h",
+                  "paper_1006_2566_amd/csrc/hsg_internal.h",
+                  "paper_1006_2566_amd/csrc/kernels_sweep.hip")
+TRAFFIC_FILE = "profiles/traffic_metropolis_pass_L256_f32.txt"
 
 
 def parse():
@@ -52,9 +72,92 @@ def parse():
     ap.add_argument("--serve-step", type=int, default=16, help="sweeps per scheduling step")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
-                         "(calibrates FETCH_SIZE / WRITE_SIZE), then 2 sweeps of the headline "
-                         "configuration; prints no JSON")
+                         "(calibrates FETCH_SIZE / WRITE_SIZE), then 2 Metropolis-only sweeps "
+                         "of the headline configuration; prints no JSON")
+    ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn the counter_collection.csv files of a FETCH_SIZE and a "
+                         "WRITE_SIZE run of --counters into the per-launch traffic summary "
+                         f"{TRAFFIC_FILE}, then exit")
     return ap.parse_args()
+
+
+def source_hash() -> str:
+    """sha256 over the sources the Metropolis pass kernel is compiled from."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_counter_csv(path):
+    """{kernel name: [value per dispatch]} of one counter from rocprofv3's CSV."""
+    import csv
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def reduce_counters(fetch_csv, write_csv):
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the Metropolis pass, each scaled
+    by what the same counter reads for the 1 GiB device copy of the --counters run."""
+    fetch, write = read_counter_csv(fetch_csv), read_counter_csv(write_csv)
+
+    def pick(d, key):
+        names = [n for n in d if key(n)]
+        if len(names) != 1:
+            raise SystemExit(f"expected one kernel, found {names}")
+        return d[names[0]]
+    def is_copy(n):
+        return "copy" in n.lower()
+
+    def mh(n):  # colour_pass_kernel<float, (hsg::PassMode)0>: binary32 Metropolis
+        return "colour_pass_kernel<float" in n and "PassMode)0>" in n
+
+    copy_f, copy_w = pick(fetch, is_copy), pick(write, is_copy)
+    mh_f, mh_w = pick(fetch, mh), pick(write, mh)
+    gib_kib = float(1 << 20)
+    f_scale = gib_kib / max(copy_f)
+    w_scale = gib_kib / max(copy_w)
+    f_b = sum(mh_f) / len(mh_f) * 1024 * f_scale
+    w_b = sum(mh_w) / len(mh_w) * 1024 * w_scale
+    lines = [
+        "# HBM traffic of one Metropolis colour pass, L=256 binary32, k=4 (counter runs)",
+        f"# commands: rocprofv3 --pmc FETCH_SIZE -d <dir> --output-format csv -- "
+        f"python bench.py --counters   (then the same with WRITE_SIZE)",
+        f"#           python bench.py --reduce-counters <fetch csv> <write csv>",
+        f"copy_fetch_kib={max(copy_f):.0f} fetch_scale={f_scale:.4f}",
+        f"copy_write_kib={max(copy_w):.0f} write_scale={w_scale:.4f}",
+        f"dispatches={len(mh_f)}",
+        f"fetch_bytes_per_launch={f_b:.0f}",
+        f"write_bytes_per_launch={w_b:.0f}",
+        f"algorithmic_bytes_per_launch={(1 << 23) * BYTES_PER_SITE_PHASE:.0f}",
+        f"source_hash={source_hash()}",
+    ]
+    with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def measured_traffic():
+    """Copy-calibrated HBM bytes per Metropolis pass launch from the committed counter
+    summary, or None when the kernel sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if "=" in line and not line.startswith("#"):
+                for item in line.split():
+                    k, _, v = item.partition("=")
+                    kv[k] = v
+    if kv.get("source_hash") != source_hash():
+        return None
+    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
 def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup, flags=0):
@@ -188,6 +291,9 @@ def cpu_baseline(args):
 
 def main():
     args = parse()
+    if args.reduce_counters:
+        reduce_counters(*args.reduce_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for "
               f"--gpus {args.gpus})", file=sys.stderr)
@@ -206,7 +312,7 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)  # 1 GiB read + 1 GiB written
         torch.cuda.synchronize()
-        lat.sweep(T=args.T, k=args.k, n_or=args.n_or, renorm_every=R, n_sweeps=2, flags=flags)
+        lat.sweep(T=args.T, k=args.k, n_or=0, renorm_every=0, n_sweeps=2, flags=flags)
         torch.cuda.synchronize()
         return
 
@@ -221,20 +327,33 @@ def main():
                          "hbm_frac_36B": N * (1 + args.n_or) * BYTES_PER_SITE_PHASE /
                          (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
-    # dominant kernel: the Metropolis colour pass.  Average duration of one such pass,
-    # timed alone (k hits, no over-relaxation) with events on the launch stream.
-    ms_mh_sweep = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=args.steps,
-                              warmup=2, flags=flags)
-    ms_pass = ms_mh_sweep / 2.0
+    # dominant kernel: the Metropolis colour pass (half the sites, k hits each).  Its
+    # average duration: Metropolis-only sweeps (two passes each, one energy fold per
+    # call) timed with events on the launch stream.  The over-relaxation pass, bound
+    # by HBM, is timed the same way.
+    ms_mh_pass = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=args.steps,
+                             warmup=2, flags=flags) / 2.0
+    ms_or_pass = time_sweeps(lat, torch, T=args.T, k=0, n_or=1, R=0, steps=args.steps,
+                             warmup=2, flags=flags) / 2.0
     head = per_k[str(args.k)]
-    bytes_pass = N / 2 * BYTES_PER_SITE_PHASE * 2 / 2  # 36 B per site-phase, half the sites
-    roofline = {"bound": "hbm", "achieved": bytes_pass / (ms_pass * 1e-3) / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": bytes_pass / (ms_pass * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
-                "kernel": "colour_pass_kernel<float, Metropolis>",
-                "kernel_ms": ms_pass}
+    sites_pass = N / 2
+    ops_pass = sites_pass * (OPS_PER_SITE + OPS_PER_HIT * args.k)
+    achieved = ops_pass / (ms_mh_pass * 1e-3) / 1e12
+    traffic = measured_traffic() if (L == 256 and args.k == 4) else None
+    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
+                "kernel": "colour_pass_kernel<float, Metropolis>", "kernel_ms": ms_mh_pass,
+                "ops_per_launch": ops_pass,
+                "hits_per_ns": sites_pass * args.k / (ms_mh_pass * 1e6),
+                "hbm_frac_36B": sites_pass * BYTES_PER_SITE_PHASE / (ms_mh_pass * 1e-3) / 1e9 /
+                HBM_PEAK_GBS,
+                "overrelax_pass": {"bound": "hbm", "kernel_ms": ms_or_pass,
+                                   "achieved_GBs": sites_pass * BYTES_PER_SITE_PHASE /
+                                   (ms_or_pass * 1e-3) / 1e9,
+                                   "frac": sites_pass * BYTES_PER_SITE_PHASE /
+                                   (ms_or_pass * 1e-3) / 1e9 / HBM_PEAK_GBS}}
 
-    rec = {"metric": "spin updates/ns at L=256 FP32 (k=1,4,8) + %HBM roofline",
+    rec = {"metric": METRIC,
            "value": head["spin_updates_per_ns"], "unit": "spin updates/ns", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",

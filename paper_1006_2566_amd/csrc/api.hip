@@ -79,7 +79,7 @@ int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hi
         a.reverse = snake ? (pass_count & 1) : 0;
         ++pass_count;
         int rc = device_status(
-            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, false, a, st),
+            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, a, st),
             "colour pass");
         if (rc) return rc;
       }

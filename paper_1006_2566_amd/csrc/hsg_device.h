@@ -19,20 +19,30 @@ struct Word4 {
   uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ c as one vector instruction (v_bitop3_b32 with the truth table of a
+// three-way exclusive or).  Worth it only when two operands are per-lane values: a
+// wave-uniform pair is folded on the scalar unit first, for one vector xor.
+__device__ __forceinline__ uint32_t xor3_v(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Philox4x32-10 (Salmon et al., SC'11).  Each round takes two 32x32->64 products
 // of counter words 0 and 2 with the round multipliers and mixes their halves with
 // words 1 and 3 and the key; the key advances by the Weyl constants between rounds.
 // Callers put the only per-lane word (the site) in word 1 and wave-uniform values in
 // words 0, 2, 3 and the key: the products of the first rounds then stay on the
-// scalar unit (16 vector products per block instead of 18).
+// scalar unit, and the mixing xors of the first rounds have a uniform pair.  From
+// round 3 (word 1's mix) and round 4 (word 3's) on, both non-key operands are per-lane.
 __device__ __forceinline__ Word4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                           uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int round = 0; round < 10; ++round) {
     const uint64_t a = (uint64_t)c0 * 0xD2511F53u;
     const uint64_t b = (uint64_t)c2 * 0xCD9E8D57u;
-    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = round >= 3 ? xor3_v((uint32_t)(b >> 32), c1, k0)
+                                   : (uint32_t)(b >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = round >= 4 ? xor3_v((uint32_t)(a >> 32), c3, k1)
+                                   : (uint32_t)(a >> 32) ^ c3 ^ k1;
     c1 = (uint32_t)b;
     c3 = (uint32_t)a;
     c0 = n0;
@@ -49,9 +59,21 @@ template <typename R>
 __device__ __forceinline__ R odd_part(uint32_t w) {
   return (R)(((w >> 9) << 1) | 1u);  // < 2^24, exactly representable
 }
+// f = 1 + m 2^-23 for the top 23 bits m of w: the exponent field of 1.0 funnel-shifted
+// in above them, one v_alignbit_b32.  The binary32 forms below derive every uniform of
+// a hit from f exactly; they give the same bits as the integer-conversion route.
+__device__ __forceinline__ float one_plus_top23(uint32_t w) {
+  return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u));
+}
+
 template <typename R>
 __device__ __forceinline__ R unit_uniform(uint32_t w) {
   return odd_part<R>(w) * (R)0x1p-24;
+}
+// u = (2m + 1) 2^-24 = f - (1 - 2^-24): both operands in [1/2, 2], so exact (Sterbenz).
+template <>
+__device__ __forceinline__ float unit_uniform<float>(uint32_t w) {
+  return one_plus_top23(w) - 0x1.fffffep-1f;
 }
 
 template <typename R>
@@ -157,6 +179,27 @@ __device__ __forceinline__ void sincos_2pi_t(R t, R& s_out, R& c_out) {
   s_out = (quadrant >= 2) ? -sq : sq;
 }
 
+// Binary32: the quadrant rotation on the bit patterns, with three-input bitwise
+// operations (v_bitop3_b32; the truth-table byte is the function applied to the
+// operand masks 0xF0, 0xCC, 0xAA).  Bit 0 of q exchanges the pair (select on a
+// 0 / all-ones mask, table 0xCA = a ? b : c); bit 1 of q flips the sign of sin and
+// bit 1 of q + 1 the sign of cos (table 0x6A = (a & b) ^ c on the sign bit).
+template <>
+__device__ __forceinline__ void sincos_2pi_t<float>(float t, float& s_out, float& c_out) {
+  const float q = rintf(t);
+  const float r = t - q;
+  float s, c;
+  Trig<float>::eval(r, s, c);
+  const int32_t qi = (int32_t)q;
+  const uint32_t odd = (uint32_t)__builtin_amdgcn_sbfe(qi, 0, 1);  // 0 or ~0
+  const uint32_t sb = __float_as_uint(s), cb = __float_as_uint(c);
+  const uint32_t sq = __builtin_amdgcn_bitop3_b32(odd, cb, sb, 0xCA);  // odd: sin <- cos
+  const uint32_t cq = __builtin_amdgcn_bitop3_b32(odd, sb, cb, 0xCA);
+  s_out = __uint_as_float(__builtin_amdgcn_bitop3_b32((uint32_t)qi << 30, 0x80000000u, sq, 0x6A));
+  c_out = __uint_as_float(
+      __builtin_amdgcn_bitop3_b32((uint32_t)(qi + 1) << 30, 0x80000000u, cq, 0x6A));
+}
+
 template <typename R>
 struct Vec3 {
   R x, y, z;
@@ -204,6 +247,17 @@ __device__ __forceinline__ Vec3<R> sphere_point_words(uint32_t w0, uint32_t w1) 
   R s, c;
   sincos_2pi_t(odd_part<R>(w1) * (R)0x1p-22, s, c);
   return Vec3<R>{rho * c, rho * s, z};
+}
+// Binary32: with f = 1 + m 2^-23 from each word, 2u - 1 = (2f - 2) - (1 - 2^-23) (the
+// product-difference m 2^-22 is exact, and so is the difference, a multiple of 2^-23
+// below 1 in magnitude) and 4u = 4f - (4 - 2^-22) in one exact fused multiply-add.
+template <>
+__device__ __forceinline__ Vec3<float> sphere_point_words<float>(uint32_t w0, uint32_t w1) {
+  const float z = fmaf(one_plus_top23(w0), 2.0f, -2.0f) - 0x1.fffffcp-1f;
+  const float rho = sqrt_rn_normal(fmaf(-z, z, 1.0f));
+  float s, c;
+  sincos_2pi_t(fmaf(one_plus_top23(w1), 4.0f, -0x1.fffffep+1f), s, c);
+  return Vec3<float>{rho * c, rho * s, z};
 }
 
 // Exact draw from the conditional law exp(beta sigma.h) on the sphere.  With

@@ -67,8 +67,7 @@ struct PassArgs {
 };
 
 template <typename R>
-hipError_t launch_colour_pass(PassMode mode, bool stream_spins, const PassArgs<R>& a,
-                              hipStream_t stream);
+hipError_t launch_colour_pass(PassMode mode, const PassArgs<R>& a, hipStream_t stream);
 
 // *E += sum of the n partials (fixed order); the partials are then zeroed.
 hipError_t launch_fold_partials(double* partials, int32_t n, double* E, hipStream_t stream);

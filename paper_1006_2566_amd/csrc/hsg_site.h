@@ -57,20 +57,6 @@ __device__ __forceinline__ void init_site(int32_t L, int64_t e, uint32_t k0, uin
   J[base + 2 * Nh] = r23 * cs;
 }
 
-// Spin accesses, optionally with the non-temporal hint.
-template <bool NT, typename R>
-__device__ __forceinline__ R load_spin(const R* p) {
-  if constexpr (NT) return __builtin_nontemporal_load(p);
-  return *p;
-}
-template <bool NT, typename R>
-__device__ __forceinline__ void store_spin(R v, R* p) {
-  if constexpr (NT)
-    __builtin_nontemporal_store(v, p);
-  else
-    *p = v;
-}
-
 // Where a site sits: colour c, column xh of its colour row, row y, plane z.
 struct SitePos {
   int32_t L, Lh, c, xh, y, z;
@@ -86,7 +72,7 @@ struct HitCtx {
 };
 
 // Updates the site in place; returns the sum of the accepted energy changes.
-template <typename R, PassMode MODE, bool NT>
+template <typename R, PassMode MODE>
 __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R>& J,
                                               const SitePos& q, const HitCtx<R>& hc) {
   const int32_t L = q.L, Lh = q.Lh, c = q.c, xh = q.xh, y = q.y, z = q.z;
@@ -110,17 +96,17 @@ __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const R* sn = S.p[nc + k];
-    R acc = j_px * load_spin<NT>(sn + n_px);
-    acc = dev_fma(j_mx, load_spin<NT>(sn + n_mx), acc);
-    acc = dev_fma(j_py, load_spin<NT>(sn + n_py), acc);
-    acc = dev_fma(j_my, load_spin<NT>(sn + n_my), acc);
-    acc = dev_fma(j_pz, load_spin<NT>(sn + n_pz), acc);
-    acc = dev_fma(j_mz, load_spin<NT>(sn + n_mz), acc);
+    R acc = j_px * *(sn + n_px);
+    acc = dev_fma(j_mx, *(sn + n_mx), acc);
+    acc = dev_fma(j_py, *(sn + n_py), acc);
+    acc = dev_fma(j_my, *(sn + n_my), acc);
+    acc = dev_fma(j_pz, *(sn + n_pz), acc);
+    acc = dev_fma(j_mz, *(sn + n_mz), acc);
     hcomp[k] = acc;
   }
   const Vec3<R> h{hcomp[0], hcomp[1], hcomp[2]};
-  Vec3<R> s{load_spin<NT>(S.p[oc + 0] + own), load_spin<NT>(S.p[oc + 1] + own),
-            load_spin<NT>(S.p[oc + 2] + own)};
+  Vec3<R> s{*(S.p[oc + 0] + own), *(S.p[oc + 1] + own),
+            *(S.p[oc + 2] + own)};
 
   double dE_sum = 0.0;
   if constexpr (MODE == PassMode::OverRelax) {
@@ -152,9 +138,9 @@ __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R
       }
     }
   }
-  store_spin<NT>(s.x, S.p[oc + 0] + own);
-  store_spin<NT>(s.y, S.p[oc + 1] + own);
-  store_spin<NT>(s.z, S.p[oc + 2] + own);
+  S.p[oc + 0][own] = s.x;
+  S.p[oc + 1][own] = s.y;
+  S.p[oc + 2][own] = s.z;
   return dE_sum;
 }
 

@@ -101,7 +101,7 @@ __device__ __forceinline__ double chain_pass(const ChainView<R>& v, const HitCtx
     const uint32_t zq = by_l.div(r);
     q.y = (int32_t)(r - zq * (uint32_t)v.L);
     q.z = (int32_t)zq;
-    dE += update_site<R, MODE, false>(v.S, v.J, q, hc);
+    dE += update_site<R, MODE>(v.S, v.J, q, hc);
   }
   return dE;
 }
@@ -346,11 +346,11 @@ __global__ __launch_bounds__(1024) void multi_pass_kernel(MultiPassArgs<R> a) {
     q.y = (int32_t)(r - zq * (uint32_t)v.L);
     q.z = (int32_t)zq;
     if (a.phase > 0)
-      update_site<R, PassMode::OverRelax, false>(v.S, v.J, q, hc);
+      update_site<R, PassMode::OverRelax>(v.S, v.J, q, hc);
     else if (ch.flags & HSG_HEAT_BATH)
-      dE = update_site<R, PassMode::HeatBath, false>(v.S, v.J, q, hc);
+      dE = update_site<R, PassMode::HeatBath>(v.S, v.J, q, hc);
     else
-      dE = update_site<R, PassMode::Metropolis, false>(v.S, v.J, q, hc);
+      dE = update_site<R, PassMode::Metropolis>(v.S, v.J, q, hc);
   }
   if (a.phase == 0) {
     const double total = group_sum(dE, s_red);

@@ -52,7 +52,7 @@ __device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
   return xcd * q + min(xcd, r) + local;
 }
 
-template <typename R, PassMode MODE, bool NT>
+template <typename R, PassMode MODE>
 __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
   const Geometry& g = a.g;
   int32_t tile = xcd_tile((int32_t)blockIdx.x, g.n_blocks);
@@ -73,7 +73,7 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
   const HitCtx<R> hc{a.beta, a.sweep, a.phase, a.k_hits, a.seed_lo, a.seed_hi};
 
   double dE_sum = 0.0;
-  if (active) dE_sum = update_site<R, MODE, NT>(a.spins, a.J, q, hc);
+  if (active) dE_sum = update_site<R, MODE>(a.spins, a.J, q, hc);
 
   if constexpr (MODE != PassMode::OverRelax) {
     __shared__ double wave_part[4];
@@ -84,38 +84,25 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
   }
 }
 
-template <typename R, bool NT>
-static void launch_mode(PassMode mode, const PassArgs<R>& a, hipStream_t stream) {
+template <typename R>
+hipError_t launch_colour_pass(PassMode mode, const PassArgs<R>& a, hipStream_t stream) {
   const dim3 grid((unsigned)a.g.n_blocks), block(256);
   switch (mode) {
     case PassMode::Metropolis:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis, NT>), grid, block, 0, stream,
-                         a);
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis>), grid, block, 0, stream, a);
       break;
     case PassMode::OverRelax:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::OverRelax, NT>), grid, block, 0, stream,
-                         a);
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::OverRelax>), grid, block, 0, stream, a);
       break;
     case PassMode::HeatBath:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::HeatBath, NT>), grid, block, 0, stream,
-                         a);
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::HeatBath>), grid, block, 0, stream, a);
       break;
   }
-}
-
-template <typename R>
-hipError_t launch_colour_pass(PassMode mode, bool stream_spins, const PassArgs<R>& a,
-                              hipStream_t stream) {
-  if (stream_spins)
-    launch_mode<R, true>(mode, a, stream);
-  else
-    launch_mode<R, false>(mode, a, stream);
   return hipGetLastError();
 }
 
-template hipError_t launch_colour_pass<float>(PassMode, bool, const PassArgs<float>&, hipStream_t);
-template hipError_t launch_colour_pass<double>(PassMode, bool, const PassArgs<double>&,
-                                                hipStream_t);
+template hipError_t launch_colour_pass<float>(PassMode, const PassArgs<float>&, hipStream_t);
+template hipError_t launch_colour_pass<double>(PassMode, const PassArgs<double>&, hipStream_t);
 
 // *E += sum of the partials in a fixed order (strided per thread, then a fixed tree),
 // and the partials are reset to zero for the next sweeps.

@@ -157,7 +157,7 @@ class Server:
         self.m_buf = torch.zeros((n_slots, 15), dtype=torch.float64, device=dev)
         # where the wall time of run() goes (seconds) and how full the steps were
         self.stats = {"steps": 0, "t_admit": 0.0, "t_step": 0.0, "t_wait": 0.0, "t_retire": 0.0,
-                      "t_idle": 0.0, "active_sum": 0, "tiles_sum": 0, "site_sweeps": 0.0}
+                      "t_idle": 0.0, "active_sum": 0, "tiles_sum": 0}
 
     # ------------------------------------------------------------------ slots
     def _set_dummy(self, s: int) -> None:
