@@ -72,8 +72,8 @@ def parse():
     ap.add_argument("--serve-step", type=int, default=16, help="sweeps per scheduling step")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
-                         "(calibrates FETCH_SIZE / WRITE_SIZE), then 2 Metropolis-only sweeps "
-                         "of the headline configuration; prints no JSON")
+                         "(calibrates FETCH_SIZE / WRITE_SIZE), then 3 sweeps of the headline "
+                         "configuration; prints no JSON")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv files of a FETCH_SIZE and a "
                          "WRITE_SIZE run of --counters into the per-launch traffic summary "
@@ -304,7 +304,7 @@ def main():
 
     L, R = args.L, args.renorm_every
     N = L ** 3
-    flags = hsg.DEFAULT_SWEEP_FLAGS if args.flags is None else args.flags
+    flags = hsg.default_flags(L) if args.flags is None else args.flags
     lat = hsg.Lattice(L, torch.float32, seed=1)
     if args.counters:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -312,7 +312,7 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)  # 1 GiB read + 1 GiB written
         torch.cuda.synchronize()
-        lat.sweep(T=args.T, k=args.k, n_or=0, renorm_every=0, n_sweeps=2, flags=flags)
+        lat.sweep(T=args.T, k=args.k, n_or=args.n_or, renorm_every=R, n_sweeps=3, flags=flags)
         torch.cuda.synchronize()
         return
 

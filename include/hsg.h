@@ -52,10 +52,20 @@ extern "C" {
 
 #define HSG_L_MAX 1290 /* largest L: N = L^3 < 2^31 keeps every site index in 32 bits */
 
-/* Sweep flags (hsg_sweep_params.flags).  HSG_SNAKE changes only the order in which
- * memory is touched, never a result. */
+/* Sweep flags (hsg_sweep_params.flags).  HSG_SNAKE and HSG_FUSED change the order in
+ * which memory is touched, never a spin; with HSG_FUSED the binary64 energy changes are
+ * summed in another (still fixed) order. */
 #define HSG_HEAT_BATH 1 /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
 #define HSG_SNAKE 2     /* successive colour passes walk the lattice in opposite z order */
+#define HSG_FUSED 4     /* run up to four consecutive colour passes per launch (binary32;
+                           two in binary64), each workgroup marching through z with its
+                           block of the lattice in LDS: the lattice is read and written once
+                           per launch instead of once per pass.  Needs L a multiple of 64
+                           with HSG_FUSED_MIN_L <= L <= HSG_FUSED_MAX_L, else ignored;
+                           overrides HSG_SNAKE.
+                           Uses the second half of the work buffer as a second spin array */
+#define HSG_FUSED_MIN_L 256
+#define HSG_FUSED_MAX_L 1024
 
 typedef struct hsg_lattice {
   int32_t L;         /* even, 2 <= L <= HSG_L_MAX */
@@ -75,7 +85,7 @@ typedef struct hsg_sweep_params {
   int32_t n_or;         /* over-relaxation phases per sweep, >= 0; k_hits + n_or >= 1 */
   int32_t renorm_every; /* R > 0: after sweep s with (s+1) % R == 0 every spin is
                            divided by its length; 0 = never */
-  int32_t flags;        /* OR of HSG_HEAT_BATH and HSG_SNAKE */
+  int32_t flags;        /* OR of HSG_HEAT_BATH, HSG_SNAKE and HSG_FUSED */
 } hsg_sweep_params;
 
 /* Sizes of the three device buffers of an L^3 lattice of the given dtype.  Any
@@ -120,9 +130,10 @@ int hsg_overlap(const hsg_lattice *a, const hsg_lattice *b, double *out_dev, voi
 
 /* ======================================================================================
  * Batched form: many independent lattices ("chains") -- disorder samples, replicas and
- * temperatures -- advanced by one persistent launch.  Each workgroup takes whole chains
- * from a device work queue and runs their sweeps with workgroup barriers between colour
- * passes; a chain computes exactly what hsg_sweep computes for the same lattice.
+ * temperatures -- advanced by one launch.  Each workgroup owns one chain and runs its
+ * sweeps with workgroup barriers between colour passes; workgroups are dispatched in
+ * the caller's order.  A chain computes exactly what hsg_sweep computes for the same
+ * lattice.
  * ==================================================================================== */
 
 #define HSG_BATCH_L_MAX 256 /* largest L of a chain in a batch */

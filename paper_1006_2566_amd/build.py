@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsg.so")
-SOURCES = ["api.hip", "kernels_sweep.hip", "kernels_lattice.hip", "kernels_batch.hip"]
+SOURCES = ["api.hip", "kernels_sweep.hip", "kernels_lattice.hip", "kernels_batch.hip",
+           "kernels_march.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HSG_OFFLOAD_ARCH", "gfx950")

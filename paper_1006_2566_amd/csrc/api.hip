@@ -51,8 +51,32 @@ int check_lattice(const hsg_lattice* lat) {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+int check_params(const hsg_sweep_params* p) {
+  if (!p) return fail(HSG_EINVAL, "sweep parameters are NULL");
+  if (!(p->T > 0.0)) return fail(HSG_EINVAL, "T must be > 0 (INFINITY for beta = 0), got %g", p->T);
+  if (p->k_hits < 0 || p->n_or < 0 || p->k_hits + p->n_or < 1)
+    return fail(HSG_EINVAL, "need k_hits >= 0, n_or >= 0 and k_hits + n_or >= 1");
+  if (p->n_or > 0x7FFF || p->k_hits > 0xFFFF)
+    return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
+  if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
+  if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE | HSG_FUSED))
+    return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
+  return HSG_OK;
+}
+
+// The colour passes of a sweep ("stages"): the Monte Carlo phase's colour-0 and
+// colour-1 passes (k_hits > 0), then two per over-relaxation phase.
+int32_t stages_per_sweep(const hsg_sweep_params* p) {
+  return 2 * ((p->k_hits > 0 ? 1 : 0) + p->n_or);
+}
+
+bool renorm_due(const hsg_sweep_params* p, uint64_t sweep) {
+  return p->renorm_every > 0 && (sweep + 1) % (uint64_t)p->renorm_every == 0;
+}
+
+// Pass-by-pass schedule: one launch per colour pass over the whole lattice.
 template <typename R>
-int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
+int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
   using namespace hsg;
   const Geometry g = pass_geometry(lat->L);
   const int64_t Nh = (int64_t)lat->L * lat->L * lat->L / 2;
@@ -79,18 +103,98 @@ int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hi
         a.reverse = snake ? (pass_count & 1) : 0;
         ++pass_count;
         int rc = device_status(
-            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, a, st),
-            "colour pass");
+            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, a, st), "colour pass");
         if (rc) return rc;
       }
     }
-    if (p->renorm_every > 0 && (sweep + 1) % (uint64_t)p->renorm_every == 0) {
-      int rc = device_status(launch_renormalise<R>(lat->L, lat->spins, st), "renormalise");
+    if (renorm_due(p, sweep)) {
+      int rc = device_status(launch_renormalise<R>(lat->L, lat->spins, 2, st), "renormalise");
       if (rc) return rc;
     }
   }
+  return HSG_OK;
+}
+
+// Fused schedule: the call's stages, sweep after sweep, cut into launches of at most
+// march_max_stages passes.  The first launch stops after the first Monte Carlo phase,
+// so that later launches end with one (its passes then carry the smallest halos, the
+// cheapest place for the expensive passes).  Each launch reads one spin array and
+// writes the other; renormalisation is folded into the passes: colour-1 spins right
+// after their last update of the sweep, colour-0 spins just before their first update
+// of the next sweep (or by a colour-0 pass at the end of the call).
+template <typename R>
+int sweep_fused(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
+  using namespace hsg;
+  if (march_blocks(lat->L) > pass_geometry(lat->L).n_blocks)
+    return fail(HSG_EUNSUPPORTED, "fused passes: more workgroups than energy partials");
+  const int32_t per = stages_per_sweep(p);
+  const int64_t total = (int64_t)per * n_sweeps;
+  const int32_t smax = march_max_stages<R>();
+  const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
+  const int32_t first_phase = p->k_hits > 0 ? 0 : 1;
+  MarchArgs<R> a{};
+  a.J = (const R*)lat->J;
+  a.partials = pass_partials(lat->work);
+  a.beta = (R)(1.0 / p->T);
+  a.seed_lo = (uint32_t)lat->seed;
+  a.seed_hi = (uint32_t)(lat->seed >> 32);
+  a.k_hits = p->k_hits;
+  a.L = lat->L;
+  R* bufs[2] = {(R*)lat->spins, (R*)((char*)lat->work + fused_offset(lat->L))};
+  int cur = 0;
+  int64_t g = 0;
+  bool first = true;
+  while (g < total) {
+    int64_t n = (first && p->k_hits > 0 && per > 2) ? 2 : smax;
+    if (n > total - g) n = total - g;
+    first = false;
+    for (int32_t i = 0; i < (int32_t)n; ++i) {
+      const int64_t gi = g + i;
+      const uint64_t sweep = lat->sweep + (uint64_t)(gi / per);
+      const int32_t s = (int32_t)(gi % per);
+      const int32_t phase = first_phase + s / 2;
+      MarchStage& m = a.st[i];
+      m.mode = (int32_t)(phase == 0 ? mc : PassMode::OverRelax);
+      m.colour = s & 1;
+      m.sweep = (uint32_t)sweep;
+      m.phase = (uint32_t)phase;
+      m.renorm_before = (s == 0 && gi >= per && renorm_due(p, sweep - 1)) ? 1 : 0;
+      m.renorm_after = (s == per - 1 && renorm_due(p, sweep)) ? 1 : 0;
+    }
+    a.in = bufs[cur];
+    a.out = bufs[1 - cur];
+    int rc = device_status(launch_march<R>(a, (int32_t)n, st), "fused passes");
+    if (rc) return rc;
+    cur = 1 - cur;
+    g += n;
+  }
+  const size_t bytes = (size_t)3 * lat->L * lat->L * lat->L * sizeof(R);
+  if (cur != 0) {
+    int rc = device_status(hipMemcpyAsync(lat->spins, bufs[cur], bytes, hipMemcpyDeviceToDevice, st),
+                           "copy spins");
+    if (rc) return rc;
+  }
+  if (n_sweeps > 0 && renorm_due(p, lat->sweep + (uint64_t)n_sweeps - 1)) {
+    int rc = device_status(launch_renormalise<R>(lat->L, lat->spins, 1, st), "renormalise");
+    if (rc) return rc;
+  }
+  return HSG_OK;
+}
+
+bool use_fused(const hsg_lattice* lat, const hsg_sweep_params* p) {
+  return (p->flags & HSG_FUSED) && hsg::march_supported(lat->L);
+}
+
+template <typename R>
+int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
+  using namespace hsg;
+  int rc = use_fused(lat, p) ? sweep_fused<R>(lat, p, n_sweeps, st)
+                             : sweep_plain<R>(lat, p, n_sweeps, st);
+  if (rc) return rc;
   if (n_sweeps > 0 && p->k_hits > 0) {
-    int rc = device_status(launch_fold_partials(a.partials, g.n_blocks, lat->E, st), "fold");
+    rc = device_status(launch_fold_partials(pass_partials(lat->work),
+                                            pass_geometry(lat->L).n_blocks, lat->E, st),
+                       "fold");
     if (rc) return rc;
   }
   return HSG_OK;
@@ -122,7 +226,7 @@ int hsg_lattice_bytes(int32_t L, int32_t dtype, size_t* spin_bytes, size_t* J_by
   const size_t n = (size_t)3 * L * L * L;
   if (spin_bytes) *spin_bytes = n * elem;
   if (J_bytes) *J_bytes = n * elem;
-  if (work_bytes) *work_bytes = hsg::work_bytes_for(L);
+  if (work_bytes) *work_bytes = hsg::work_bytes_for(L, (int32_t)elem);
   return HSG_OK;
 }
 
@@ -172,18 +276,15 @@ int hsg_export(const hsg_lattice* lat, void* canon_spins, void* canon_J, void* s
 int hsg_sweep(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, void* stream) {
   int rc = check_lattice(lat);
   if (rc) return rc;
-  if (!p) return fail(HSG_EINVAL, "sweep parameters are NULL");
-  if (!(p->T > 0.0)) return fail(HSG_EINVAL, "T must be > 0 (INFINITY for beta = 0), got %g", p->T);
-  if (p->k_hits < 0 || p->n_or < 0 || p->k_hits + p->n_or < 1)
-    return fail(HSG_EINVAL, "need k_hits >= 0, n_or >= 0 and k_hits + n_or >= 1");
-  if (p->n_or > 0x7FFF || p->k_hits > 0xFFFF)
-    return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
-  if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
-  if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE))
-    return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
+  rc = check_params(p);
+  if (rc) return rc;
   if (n_sweeps < 0) return fail(HSG_EINVAL, "n_sweeps must be >= 0");
   if (lat->sweep + (uint64_t)n_sweeps > 0x100000000ull)
     return fail(HSG_EINVAL, "sweep index would pass 2^32");
+  const size_t elem = lat->dtype == HSG_F32 ? 4 : 8;
+  if (use_fused(lat, p) && lat->work_bytes < hsg::work_bytes_for(lat->L, (int32_t)elem))
+    return fail(HSG_EINVAL, "HSG_FUSED needs a work buffer of %zu bytes (has %zu)",
+                hsg::work_bytes_for(lat->L, (int32_t)elem), lat->work_bytes);
   hipStream_t st = as_stream(stream);
   rc = lat->dtype == HSG_F32 ? sweep_impl<float>(lat, p, n_sweeps, st)
                              : sweep_impl<double>(lat, p, n_sweeps, st);

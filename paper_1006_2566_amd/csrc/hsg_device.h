@@ -323,4 +323,28 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD b % 8).
+// Renumber them so that XCD x receives one contiguous range of tiles: tiles that
+// share neighbour planes then meet in the same L2.  A bijection for any count.
+__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
+  const int32_t q = n >> 3, r = n & 7;
+  const int32_t xcd = b & 7, local = b >> 3;
+  return xcd * q + min(xcd, r) + local;
+}
+
+// Sum of a double over the workgroup (blockDim.x a multiple of 64, at most 1024):
+// wave sums, then wave 0's lane 0 adds them in wave order.  The result is valid in
+// thread 0 only.  Every thread of the workgroup must call it (two barriers).
+__device__ __forceinline__ double block_sum(double v, double* scratch16) {
+  const double w = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) scratch16[threadIdx.x >> 6] = w;
+  __syncthreads();
+  double total = 0.0;
+  if (threadIdx.x == 0) {
+    for (unsigned i = 0; i < blockDim.x / 64; ++i) total += scratch16[i];
+  }
+  __syncthreads();
+  return total;
+}
+
 }  // namespace hsg

@@ -30,7 +30,11 @@ constexpr int kReduceSlots = 16;  // doubles per block partial (overlap needs 15
 //   [0, 256)                              reserved
 //   [256, 256 + 8*n_blocks)               per-tile energy-change partials of the passes
 //   [.., + 8*kReduceBlocks*kReduceSlots)  per-block partials of energy / overlap
-size_t work_bytes_for(int32_t L);
+//   [fused_offset(L), + 3*N*sizeof(R))    second spin array of fused launches (only for
+//                                         L that march_supported accepts)
+size_t work_bytes_for(int32_t L);  // without the second spin array
+size_t fused_offset(int32_t L);    // 256-byte aligned end of the above
+size_t work_bytes_for(int32_t L, int32_t dtype_bytes);  // with it where it applies
 inline double* pass_partials(void* work) { return (double*)((char*)work + 256); }
 inline double* reduce_partials(void* work, int32_t L) {
   return pass_partials(work) + pass_geometry(L).n_blocks;
@@ -69,6 +73,41 @@ struct PassArgs {
 template <typename R>
 hipError_t launch_colour_pass(PassMode mode, const PassArgs<R>& a, hipStream_t stream);
 
+// A colour pass inside a fused launch.
+struct MarchStage {
+  int32_t mode;           // PassMode
+  int32_t colour;         // colour updated
+  uint32_t sweep, phase;  // Philox counter words
+  int32_t renorm_before;  // divide each updated spin by its length before the update
+  int32_t renorm_after;   // ... and after it
+};
+constexpr int kMarchMaxStages = 4;
+constexpr int kMarchMinL = 256;   // smaller lattices give too few workgroups
+constexpr int kMarchMaxL = 1024;  // element offsets stay below 2^32
+constexpr int kMarchZ = 64;      // planes per workgroup
+
+template <typename R>
+struct MarchArgs {
+  const R* in;       // colour-split spins before the launch's first pass
+  R* out;            // colour-split spins after its last pass (distinct from in)
+  const R* J;        // colour-split couplings
+  double* partials;  // one per workgroup, energy changes of its own sites are added
+  R beta;
+  uint32_t seed_lo, seed_hi;
+  int32_t k_hits;
+  int32_t L;
+  int32_t tiles_x, tiles_y, zc;  // set by launch_march
+  MarchStage st[kMarchMaxStages];
+};
+
+bool march_supported(int32_t L);
+int32_t march_blocks(int32_t L);
+template <typename R>
+int32_t march_max_stages();
+// n_stages consecutive passes (2, or 4 in binary32) described by a.st.
+template <typename R>
+hipError_t launch_march(const MarchArgs<R>& a, int32_t n_stages, hipStream_t stream);
+
 // *E += sum of the n partials (fixed order); the partials are then zeroed.
 hipError_t launch_fold_partials(double* partials, int32_t n, double* E, hipStream_t stream);
 
@@ -81,7 +120,7 @@ template <typename R>
 hipError_t launch_export(int32_t L, const void* spins, const void* J, R* canon_spins,
                          R* canon_J, hipStream_t stream);
 template <typename R>
-hipError_t launch_renormalise(int32_t L, void* spins, hipStream_t stream);
+hipError_t launch_renormalise(int32_t L, void* spins, int32_t colours, hipStream_t stream);
 // out[0] = H (recomputed, binary64).
 template <typename R>
 hipError_t launch_energy(int32_t L, const void* spins, const void* J, double* partials,

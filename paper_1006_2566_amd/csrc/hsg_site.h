@@ -71,6 +71,62 @@ struct HitCtx {
   uint32_t seed_lo, seed_hi;
 };
 
+// The update of one site given its spin s and local field h (eq. 2): reflection about
+// h (over-relaxation), or k Metropolis hits / heat-bath draws with h fixed, drawing
+// from Philox counter (sweep, site, phase << 16 | hit, tag).  s is replaced in place;
+// returns the sum of the accepted energy changes.
+//
+// A hit's draws, trial spin and trial energy do not depend on earlier decisions, only
+// its accept/reject step does.  With G > 1 the hits are taken G at a time: first the G
+// independent draws and trials (instruction-level parallelism for a wave with few
+// neighbours on its SIMD), then the G decisions in order.  Every operation and the
+// order of the energy sum are the same for any G.
+template <typename R, PassMode MODE, int G = 1>
+__device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uint32_t site,
+                                               const HitCtx<R>& hc) {
+  double dE_sum = 0.0;
+  if constexpr (MODE == PassMode::OverRelax) {
+    s = reflect(s, h);
+  } else {
+    const uint32_t tag = MODE == PassMode::Metropolis ? kTagMetropolis : kTagHeatBath;
+    R sh = dot3(s, h);
+    for (int32_t j0 = 0; j0 < hc.k_hits; j0 += G) {
+      Vec3<R> trial[G];
+      R th[G], u2[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (G == 1 || j0 + g < hc.k_hits) {
+          const uint32_t j = (uint32_t)(j0 + g);
+          const Word4 w = philox10(hc.sweep, site, (hc.phase << 16) | j, tag, hc.seed_lo,
+                                   hc.seed_hi);
+          if constexpr (MODE == PassMode::Metropolis) {
+            trial[g] = sphere_point_words<R>(w.w0, w.w1);
+            u2[g] = unit_uniform<R>(w.w2);
+          } else {
+            trial[g] = heat_bath_point(h, hc.beta, unit_uniform<R>(w.w0), unit_uniform<R>(w.w1));
+          }
+          th[g] = dot3(trial[g], h);
+        }
+      }
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        if (G == 1 || j0 + g < hc.k_hits) {
+          const R dE = sh - th[g];
+          bool accept = true;
+          if constexpr (MODE == PassMode::Metropolis)
+            accept = (dE <= (R)0) || (u2[g] < accept_prob(-hc.beta * dE));
+          if (accept) {
+            s = trial[g];
+            sh = th[g];
+            dE_sum += (double)dE;
+          }
+        }
+      }
+    }
+  }
+  return dE_sum;
+}
+
 // Updates the site in place; returns the sum of the accepted energy changes.
 template <typename R, PassMode MODE>
 __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R>& J,
@@ -108,40 +164,19 @@ __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R
   Vec3<R> s{*(S.p[oc + 0] + own), *(S.p[oc + 1] + own),
             *(S.p[oc + 2] + own)};
 
-  double dE_sum = 0.0;
-  if constexpr (MODE == PassMode::OverRelax) {
-    s = reflect(s, h);
-  } else {
-    const uint32_t site = (uint32_t)(2 * xh + p) + (uint32_t)L * (uint32_t)(y + L * z);
-    const uint32_t tag = MODE == PassMode::Metropolis ? kTagMetropolis : kTagHeatBath;
-    R sh = dot3(s, h);
-    for (int32_t j = 0; j < hc.k_hits; ++j) {
-      const Word4 w = philox10(hc.sweep, site, (hc.phase << 16) | (uint32_t)j, tag, hc.seed_lo,
-                               hc.seed_hi);
-      Vec3<R> trial;
-      if constexpr (MODE == PassMode::Metropolis) {
-        trial = sphere_point_words<R>(w.w0, w.w1);
-      } else {
-        trial = heat_bath_point(h, hc.beta, unit_uniform<R>(w.w0), unit_uniform<R>(w.w1));
-      }
-      const R th = dot3(trial, h);
-      const R dE = sh - th;
-      bool accept = true;
-      if constexpr (MODE == PassMode::Metropolis) {
-        const R u2 = unit_uniform<R>(w.w2);
-        accept = (dE <= (R)0) || (u2 < accept_prob(-hc.beta * dE));
-      }
-      if (accept) {
-        s = trial;
-        sh = th;
-        dE_sum += (double)dE;
-      }
-    }
-  }
+  const uint32_t site = (uint32_t)(2 * xh + p) + (uint32_t)L * (uint32_t)(y + L * z);
+  const double dE_sum = apply_update<R, MODE>(s, h, site, hc);
   S.p[oc + 0][own] = s.x;
   S.p[oc + 1][own] = s.y;
   S.p[oc + 2][own] = s.z;
   return dE_sum;
+}
+
+// s / |s| (length from a fused dot product, correctly rounded root and divisions).
+template <typename R>
+__device__ __forceinline__ Vec3<R> unit_vector(const Vec3<R>& s) {
+  const R n = dev_sqrt(dot3(s, s));
+  return Vec3<R>{dev_div(s.x, n), dev_div(s.y, n), dev_div(s.z, n)};
 }
 
 // sigma <- sigma / |sigma| for the spin at index e of colour c (N/2 = Nh per colour).

@@ -30,27 +30,6 @@ struct SmallDiv {
   __device__ __forceinline__ uint32_t div(uint32_t n) const { return d > 1 ? __umulhi(n, m) : n; }
 };
 
-// Workgroups go to the 8 XCDs round-robin; renumber tiles so each XCD takes one
-// contiguous range (neighbouring tiles of a chain then share its L2).  A bijection.
-__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
-  const int32_t q = n >> 3, r = n & 7;
-  const int32_t xcd = b & 7, local = b >> 3;
-  return xcd * q + min(xcd, r) + local;
-}
-
-// Sum of v over the workgroup (waves in order, lanes by butterfly), valid on thread 0.
-__device__ __forceinline__ double group_sum(double v, double* scratch16) {
-  const double w = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) scratch16[threadIdx.x >> 6] = w;
-  __syncthreads();
-  double total = 0.0;
-  if (threadIdx.x == 0) {
-    for (unsigned i = 0; i < (blockDim.x + 63) / 64; ++i) total += scratch16[i];
-  }
-  __syncthreads();
-  return total;
-}
-
 template <typename R>
 struct ChainView {
   Planes<R> S, J;
@@ -183,7 +162,7 @@ __global__ __launch_bounds__(1024) void batch_sweep_kernel(BatchArgs<R> a) {
       __syncthreads();
     }
   }
-  const double total = group_sum(dE, s_red);
+  const double total = block_sum(dE, s_red);
   if (threadIdx.x == 0) {
     a.E[ci] += total;
     a.sweep[ci] = sweep0 + (uint32_t)n;
@@ -215,7 +194,7 @@ __global__ __launch_bounds__(256) void batch_energy_kernel(const hsg_chain* chai
     const SiteOf st = site_of(e, L);
     acc += colour0_bond_sum(spins + ch.spin_offset, J + ch.J_offset, Nh, L, Lh, st.xh, st.y, st.z);
   }
-  const double total = group_sum(acc, s_red);
+  const double total = block_sum(acc, s_red);
   if (threadIdx.x == 0) out[blockIdx.x] = -total;
 }
 
@@ -243,7 +222,7 @@ __device__ __forceinline__ void pair_overlap(const hsg_chain& ca, const hsg_chai
     }
   }
   for (int k = 0; k < 15; ++k) {
-    const double t = group_sum(v[k], s_red);
+    const double t = block_sum(v[k], s_red);
     if (threadIdx.x == 0) out[k] = t / (double)N;
   }
 }
@@ -353,7 +332,7 @@ __global__ __launch_bounds__(1024) void multi_pass_kernel(MultiPassArgs<R> a) {
       dE = update_site<R, PassMode::Metropolis>(v.S, v.J, q, hc);
   }
   if (a.phase == 0) {
-    const double total = group_sum(dE, s_red);
+    const double total = block_sum(dE, s_red);
     if (threadIdx.x == 0 && total != 0.0) atomicAdd(&a.E[ci], total);
   }
 }

@@ -58,8 +58,9 @@ __global__ __launch_bounds__(256) void export_kernel(int32_t L, const R* spins, 
 // sigma <- sigma / |sigma| (length from a fused dot product, correctly rounded root
 // and divisions).
 template <typename R>
-__global__ __launch_bounds__(256) void renormalise_kernel(int64_t Nh, R* spins) {
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < 2 * Nh;
+__global__ __launch_bounds__(256) void renormalise_kernel(int64_t Nh, int32_t colours,
+                                                          R* spins) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < colours * Nh;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t c = e >= Nh ? 1 : 0;
     const int64_t base = 3 * c * Nh + (e - c * Nh);
@@ -187,10 +188,10 @@ hipError_t launch_export(int32_t L, const void* spins, const void* J, R* canon_s
 }
 
 template <typename R>
-hipError_t launch_renormalise(int32_t L, void* spins, hipStream_t stream) {
+hipError_t launch_renormalise(int32_t L, void* spins, int32_t colours, hipStream_t stream) {
   const int64_t Nh = (int64_t)L * L * L / 2;
-  hipLaunchKernelGGL(renormalise_kernel<R>, dim3(grid_for(2 * Nh, 256)), dim3(256), 0, stream,
-                     Nh, (R*)spins);
+  hipLaunchKernelGGL(renormalise_kernel<R>, dim3(grid_for(colours * Nh, 256)), dim3(256), 0,
+                     stream, Nh, colours, (R*)spins);
   return hipGetLastError();
 }
 
@@ -237,7 +238,7 @@ hipError_t launch_copy_double(const double* src, double* dst, hipStream_t stream
   template hipError_t launch_init<R>(int32_t, uint64_t, void*, void*, hipStream_t);           \
   template hipError_t launch_import<R>(int32_t, const R*, const R*, void*, void*, hipStream_t); \
   template hipError_t launch_export<R>(int32_t, const void*, const void*, R*, R*, hipStream_t); \
-  template hipError_t launch_renormalise<R>(int32_t, void*, hipStream_t);                     \
+  template hipError_t launch_renormalise<R>(int32_t, void*, int32_t, hipStream_t);                     \
   template hipError_t launch_energy<R>(int32_t, const void*, const void*, double*, double*,   \
                                        hipStream_t);                                          \
   template hipError_t launch_overlap<R>(int32_t, const void*, const void*, double*, double*,  \

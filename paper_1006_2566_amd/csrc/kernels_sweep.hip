@@ -43,13 +43,11 @@ size_t work_bytes_for(int32_t L) {
                                  (size_t)kReduceBlocks * kReduceSlots);
 }
 
-// Workgroups are dispatched to the 8 XCDs round-robin (block b runs on XCD b % 8).
-// Renumber them so that XCD x receives one contiguous range of tiles: tiles that
-// share neighbour planes then meet in the same L2.  A bijection for any count.
-__device__ __forceinline__ int32_t xcd_tile(int32_t b, int32_t n) {
-  const int32_t q = n >> 3, r = n & 7;
-  const int32_t xcd = b & 7, local = b >> 3;
-  return xcd * q + min(xcd, r) + local;
+size_t fused_offset(int32_t L) { return (work_bytes_for(L) + 255) & ~(size_t)255; }
+
+size_t work_bytes_for(int32_t L, int32_t dtype_bytes) {
+  if (!march_supported(L)) return work_bytes_for(L);
+  return fused_offset(L) + (size_t)3 * L * L * L * (size_t)dtype_bytes;
 }
 
 template <typename R, PassMode MODE>

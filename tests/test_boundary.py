@@ -82,7 +82,7 @@ def test_null_and_missing_buffers_rejected(hsg):
 @pytest.mark.parametrize("T,k,n_or,R,flags,n", [
     (0.0, 1, 0, 0, 0, 1), (-1.0, 1, 0, 0, 0, 1), (float("nan"), 1, 0, 0, 0, 1),
     (1.0, 0, 0, 0, 0, 1), (1.0, -1, 1, 0, 0, 1), (1.0, 1, -1, 0, 0, 1),
-    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 4, 1),
+    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 16, 1),
     (1.0, 70000, 0, 0, 0, 1)])
 def test_sweep_rejects_bad_params(hsg, T, k, n_or, R, flags, n):
     lib = hsg.lib()
@@ -90,6 +90,18 @@ def test_sweep_rejects_bad_params(hsg, T, k, n_or, R, flags, n):
     p = hsg._SweepParams(T, k, n_or, R, flags)
     assert lib.hsg_sweep(ctypes.byref(d), ctypes.byref(p), n, None) == -1
     assert d.sweep == 0
+
+
+def test_fused_needs_the_larger_work_buffer(hsg):
+    lib = hsg.lib()
+    full = hsg.lattice_bytes(256)[2]
+    assert full >= 3 * 256 ** 3 * 4
+    d = _desc(hsg, L=256, work_bytes=full - 4)
+    p = hsg._SweepParams(1.0, 1, 0, 0, hsg.HSG_FUSED)
+    assert lib.hsg_sweep(ctypes.byref(d), ctypes.byref(p), 1, None) == -1
+    assert b"HSG_FUSED" in lib.hsg_last_error()
+    # lattices the fused passes do not cover need no second spin array
+    assert hsg.lattice_bytes(96)[2] < 3 * 96 ** 3 * 4
 
 
 def test_sweep_counter_overflow_rejected(hsg):
@@ -109,14 +121,11 @@ def test_overlap_requires_matching_lattices(hsg):
 
 
 def test_product_path_has_no_fallback(tmp_path, monkeypatch):
-    import importlib
-
     import paper_1006_2566_amd as m
     monkeypatch.setattr(m, "LIB_PATH", str(tmp_path / "missing.so"))
     monkeypatch.setattr(m, "_lib", None)
     with pytest.raises(ImportError):
         m.lib()
-    importlib.reload(m)
 
 
 # ------------------------------------------------------------------ batched form
@@ -193,3 +202,4 @@ def test_pt_workload_shape():
     assert Ls <= {16, 24, 32, 48}
     # a sample's 48 chains share one coupling group and one L
     assert len({(s.J_group, s.L) for s in specs}) == 256
+

@@ -190,16 +190,19 @@ def test_heat_bath_binary32_matches_oracle(hsg, L, T, k):
     assert np.all(err <= 1e-5 * np.maximum(1.0, 0.05 / rho) * scale)
 
 
-@pytest.mark.parametrize("k", [1, 4, 8])
-def test_full_size_sweep_matches_oracle(hsg, k):
+@pytest.mark.parametrize("k,fused", [(1, False), (4, False), (8, False), (4, True)])
+def test_full_size_sweep_matches_oracle(hsg, k, fused):
     """L = 256 (16.8M spins), binary32, the launch configuration the benchmark
-    times (hsg_sweep's colour passes): one sweep of k hits + 1 over-relaxation phase
-    from a seeded state, every site compared."""
+    times (hsg_sweep's colour passes, or the fused passes): one sweep of k hits + 1
+    over-relaxation phase from a seeded state, every site compared."""
     L, seed = 256, 1
     s, J = inputs.random_state(L, 256, F32)
-    got, E_gpu, _ = gpu_run(hsg, L, seed, s, J, T=0.3, k=k, n_or=1)
+    lat = hsg.Lattice(L, torch.float32, seed=seed, init=None)
+    lat.load(torch.from_numpy(s), torch.from_numpy(J))
+    lat.sweep(T=0.3, k=k, n_or=1, flags=hsg.HSG_FUSED if fused else None)
+    got, E_gpu = lat.export()[0].cpu().numpy(), lat.energy().item()
     ref, r, taint = oracle_run(L, seed, s, J, T=0.3, k=k, n_or=1)
-    compare(got, ref, taint, F32, f"L=256 k={k} flagged={r['n_flagged']}", 0.001)
+    compare(got, ref, taint, F32, f"L=256 k={k} fused={fused} flagged={r['n_flagged']}", 0.001)
     assert abs(E_gpu - r["E"]) <= 1e-5 * abs(r["E"])
 
 
@@ -298,3 +301,29 @@ def test_infinite_temperature_uniform(hsg):
     s = lat.export()[0].cpu().numpy()
     for a in range(3):
         assert stats.kstest(s[a], stats.uniform(loc=-1, scale=2).cdf).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("L,dtype,k,n_or,R,hb,n", [
+    (256, F32, 4, 1, 10, False, 3), (256, F32, 1, 2, 1, False, 3), (256, F32, 8, 0, 2, False, 5),
+    (256, F32, 0, 3, 0, False, 2), (256, F32, 2, 1, 1, True, 2), (320, F32, 4, 1, 3, False, 4),
+    (256, F64, 4, 1, 2, False, 2)])
+def test_fused_passes_equal_pass_by_pass(hsg, L, dtype, k, n_or, R, hb, n):
+    """The fused z-marching launches (several colour passes per launch, halos
+    recomputed by neighbouring workgroups, renormalisation folded into the passes)
+    reproduce the pass-by-pass schedule: spins bit for bit, the sweep counter exactly,
+    the tracked energy up to the order of its binary64 sums."""
+    s, J = inputs.random_state(L, 9 * L + k, dtype)
+    runs = []
+    for flags in (0, hsg.HSG_FUSED):
+        lat = hsg.Lattice(L, tdtype(dtype), seed=11, init=None)
+        lat.load(torch.from_numpy(s), torch.from_numpy(J))
+        lat.sweep_index = 7
+        lat.sweep(T=0.4, k=k, n_or=n_or, renorm_every=R, n_sweeps=n, heat_bath=hb, flags=flags)
+        runs.append((lat.export()[0], lat.energy().item(), lat.sweep_index))
+    (s0, E0, i0), (s1, E1, i1) = runs
+    same = (s0 == s1).all(dim=0).float().mean().item()
+    print(f"[parity] fused L={L} {np.dtype(dtype).name} k={k} n_or={n_or} R={R} hb={hb} "
+          f"n={n}: bitwise={same:.6f} E={E0:.9f} dE={E1 - E0:.3e}", flush=True)
+    assert torch.equal(s0, s1)
+    assert i0 == i1
+    assert abs(E1 - E0) <= 1e-12 * abs(E0)
