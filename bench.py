@@ -64,12 +64,17 @@ def parse():
     ap.add_argument("--batch-cycles", type=int, default=2,
                     help="timed cycles (100 sweeps each) of the batched tempering workload; "
                          "0 skips that leg")
-    ap.add_argument("--batch-threads", type=int, default=256)
+    ap.add_argument("--batch-threads", type=int, default=0,
+                    help="workgroup size of the batched sweep (0 = autotuned)")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the served stream (0 skips that leg)")
     ap.add_argument("--serve-budget-mb", type=int, default=8192,
                     help="device memory for resident lattices of the served stream")
     ap.add_argument("--serve-step", type=int, default=16, help="sweeps per scheduling step")
+    ap.add_argument("--serve-tile", type=int, default=0,
+                    help="sites per tile of the served passes (0 = autotuned)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the library defaults instead of timing candidate launch shapes")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
                          "(calibrates FETCH_SIZE / WRITE_SIZE), then 3 sweeps of the headline "
@@ -186,7 +191,10 @@ def batched_leg(args, torch):
     from paper_1006_2566_amd import batch as B
 
     specs, ladders, betas, pairs = B.pt_workload()
-    b = B.Batch(specs, threads=args.batch_threads)
+    b = B.Batch(specs, threads=args.batch_threads or 256)
+    if not args.batch_threads and not args.no_autotune:
+        from paper_1006_2566_amd import autotune
+        autotune.batch_threads(b)
     pt = B.Tempering(b, ladders, betas, seed=1)
     runner = B.PTRunner(b, pt, pairs, sweeps_per_exchange=10, exchanges_per_measure=10)
     runner.run_cycle()  # eager first cycle, then the graph is captured
@@ -228,7 +236,7 @@ def batched_leg(args, torch):
             "plain_per_lattice_updates_per_ns": upd_plain,
             "speedup_vs_plain": upd / upd_plain,
             "exchange_acceptance_per_pair_round": acc,
-            "threads": args.batch_threads}
+            "threads": b.threads}
 
 
 def served_leg(args, torch):
@@ -241,8 +249,12 @@ def served_leg(args, torch):
     from paper_1006_2566_amd import serve as S
 
     trace = S.poisson_trace(n=args.serve_requests, rate=200.0, seed=1)
+    tile = args.serve_tile or 256
+    if not args.serve_tile and not args.no_autotune:
+        from paper_1006_2566_amd import autotune
+        tile = autotune.serve_shape(trace[:64])["tile_sites"]
     srv = S.Server(hbm_budget=args.serve_budget_mb << 20, n_slots=2048,
-                   step_sweeps=args.serve_step)
+                   step_sweeps=args.serve_step, tile_sites=tile)
     srv.run([S.Request(rid=-1, seed=1, L=8, T=1.0, sweeps=2, k=1)], realtime=False)  # load kernels
     t0 = time.perf_counter()
     res = srv.run(trace, realtime=True)
@@ -256,7 +268,7 @@ def served_leg(args, torch):
             "mean_latency_s": st["mean_s"], "wall_s": wall,
             "spin_updates_per_ns": upd / (wall * 1e9),
             "offered_updates_per_ns": offered, "budget_mb": args.serve_budget_mb,
-            "step_sweeps": args.serve_step,
+            "step_sweeps": args.serve_step, "tile_sites": tile,
             "scheduler": {k: (round(v, 3) if isinstance(v, float) else v)
                           for k, v in srv.stats.items()}}
 
@@ -304,7 +316,14 @@ def main():
 
     L, R = args.L, args.renorm_every
     N = L ** 3
-    flags = hsg.default_flags(L) if args.flags is None else args.flags
+    if args.flags is not None:
+        flags = args.flags
+    elif args.no_autotune or args.counters:
+        flags = hsg.default_flags(L)
+    else:
+        from paper_1006_2566_amd import autotune
+        flags = autotune.sweep_flags(L, torch.float32, k=args.k, n_or=args.n_or, T=args.T,
+                                     renorm_every=args.renorm_every)
     lat = hsg.Lattice(L, torch.float32, seed=1)
     if args.counters:
         a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -331,10 +350,11 @@ def main():
     # average duration: Metropolis-only sweeps (two passes each, one energy fold per
     # call) timed with events on the launch stream.  The over-relaxation pass, bound
     # by HBM, is timed the same way.
+    pass_flags = flags & ~hsg.HSG_FUSED  # one launch per colour pass
     ms_mh_pass = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=args.steps,
-                             warmup=2, flags=flags) / 2.0
+                             warmup=2, flags=pass_flags) / 2.0
     ms_or_pass = time_sweeps(lat, torch, T=args.T, k=0, n_or=1, R=0, steps=args.steps,
-                             warmup=2, flags=flags) / 2.0
+                             warmup=2, flags=pass_flags) / 2.0
     head = per_k[str(args.k)]
     sites_pass = N / 2
     ops_pass = sites_pass * (OPS_PER_SITE + OPS_PER_HIT * args.k)

@@ -220,3 +220,26 @@ def test_graph_replay_equals_eager(mods):
         assert torch.equal(ra.pt.chain_at_slot, rb.pt.chain_at_slot), cycle
         assert torch.equal(ra.q, rb.q), cycle
     assert int(ra.pt.round.item()) == 4 * 2
+
+
+def test_autotune_batch_threads_restores_state(mods, tmp_path):
+    """Tuning times real sweeps of the batch, then puts every chain back as it was."""
+    hsg, B = mods
+    from paper_1006_2566_amd import autotune as A
+    b = B.Batch(mixed_specs(B), track_remaining=True)
+    b.remaining.fill_(9)
+    before = (b.spins.clone(), b.E.clone(), b.sweep_ctr.clone(), b.remaining.clone())
+    t = A.batch_threads(b, path=str(tmp_path / "tune.json"))
+    assert t in (64, 128, 256, 512, 1024) and b.threads == t
+    assert torch.equal(b.spins, before[0]) and torch.equal(b.E, before[1])
+    assert torch.equal(b.sweep_ctr, before[2]) and torch.equal(b.remaining, before[3])
+    assert A.load_cache(str(tmp_path / "tune.json"))[A.device_key()]
+
+
+def test_autotune_sweep_flags(mods, tmp_path):
+    hsg, B = mods
+    from paper_1006_2566_amd import autotune as A
+    f = A.sweep_flags(64, k=2, n_or=1, path=str(tmp_path / "tune.json"))
+    assert f in (0, hsg.HSG_SNAKE)
+    f = A.sweep_flags(256, k=1, n_or=1, path=str(tmp_path / "tune.json"))
+    assert f in (0, hsg.HSG_SNAKE, hsg.HSG_FUSED)

@@ -52,3 +52,34 @@ def test_latency_stats():
     st = S.latency_stats(res)
     assert st["n"] == 100 and st["p50_s"] == pytest.approx(50.5) and st["max_s"] == 100
     assert st["p99_s"] == pytest.approx(99.01)
+
+
+def test_autotune_pick_caches_the_fastest(tmp_path):
+    from paper_1006_2566_amd import autotune as A
+    path = str(tmp_path / "tune.json")
+    calls = []
+
+    def measure(c):
+        calls.append(c)
+        return {64: 3.0, 128: 1.0, 256: 2.0}[c]
+    assert A.pick("k1", [64, 128, 256], measure, path=path, dev="gfxTEST") == 128
+    assert calls == [64, 128, 256]
+    # cached: no new measurements, even with another candidate order
+    assert A.pick("k1", [256, 128, 64], measure, path=path, dev="gfxTEST") == 128
+    assert len(calls) == 3
+    # a cached choice that is no longer a candidate is re-measured
+    assert A.pick("k1", [64, 256], measure, path=path, dev="gfxTEST") == 256
+    # retune forces new measurements; other devices keep their own entries
+    A.pick("k1", [64, 128], measure, path=path, dev="gfxTEST", retune=True)
+    A.pick("k1", [64, 256], measure, path=path, dev="gfxOTHER")
+    data = A.load_cache(path)
+    assert data["gfxTEST"]["k1"]["choice"] == 128 and data["gfxOTHER"]["k1"]["choice"] == 256
+    assert set(data["gfxTEST"]["k1"]["ms"]) == {"64", "128"}
+
+
+def test_autotune_cache_tolerates_garbage(tmp_path):
+    from paper_1006_2566_amd import autotune as A
+    path = tmp_path / "tune.json"
+    path.write_text("{not json")
+    assert A.load_cache(str(path)) == {}
+    assert A.pick("k", [1, 2], lambda c: float(c), path=str(path), dev="x") == 1
