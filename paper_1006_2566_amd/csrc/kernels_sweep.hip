@@ -105,12 +105,12 @@ __device__ __forceinline__ double update_site_b32(const Planes<float>& S, const 
   return dE_sum;
 }
 
+// One tile of a colour pass (a BX x BY x BZ block of the colour's sites); Metropolis
+// and heat-bath passes add the tile's accepted energy changes to partials[tile] in a
+// fixed order (wave sums, then the waves in order).  `tile` must be wave-uniform.
 template <typename R, PassMode MODE>
-__global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
+__device__ __forceinline__ void pass_tile(const PassArgs<R>& a, int32_t tile) {
   const Geometry& g = a.g;
-  int32_t tile = xcd_tile((int32_t)blockIdx.x, g.n_blocks);
-  if (a.reverse) tile = g.n_blocks - 1 - tile;
-  tile = __builtin_amdgcn_readfirstlane(tile);  // uniform: the tile split runs on the scalar unit
   const int32_t tx = tile % g.tiles_x;
   const int32_t rest = tile / g.tiles_x;
   const int32_t ty = rest % g.tiles_y;
@@ -141,6 +141,13 @@ __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
     __syncthreads();
     if (t == 0) a.partials[tile] += ((wave_part[0] + wave_part[1]) + (wave_part[2] + wave_part[3]));
   }
+}
+
+template <typename R, PassMode MODE>
+__global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
+  int32_t tile = xcd_tile((int32_t)blockIdx.x, a.g.n_blocks);
+  if (a.reverse) tile = a.g.n_blocks - 1 - tile;
+  pass_tile<R, MODE>(a, __builtin_amdgcn_readfirstlane(tile));
 }
 
 template <typename R>

@@ -203,3 +203,4 @@ def test_pt_workload_shape():
     # a sample's 48 chains share one coupling group and one L
     assert len({(s.J_group, s.L) for s in specs}) == 256
 
+

@@ -327,3 +327,4 @@ def test_fused_passes_equal_pass_by_pass(hsg, L, dtype, k, n_or, R, hb, n):
     assert torch.equal(s0, s1)
     assert i0 == i1
     assert abs(E1 - E0) <= 1e-12 * abs(E0)
+
