@@ -128,6 +128,31 @@ int hsg_energy(const hsg_lattice *lat, int32_t recompute, double *out_dev, void 
  * out_dev is device memory for 15 doubles.  a's work buffer is used as scratch. */
 int hsg_overlap(const hsg_lattice *a, const hsg_lattice *b, double *out_dev, void *stream);
 
+/* Spin-glass observables of two replicas a, b (same couplings, same L and dtype).
+ * The paper defines no observable; these are the standard ones of vector spin
+ * glasses, built on the local overlap tensor q_r^{mu nu} = a_r^mu b_r^nu of the
+ * model of §2.  Its Fourier components
+ *     Q^{mu nu}(k) = (1/N) sum_r q_r^{mu nu} exp(+i k.r),   r = (x, y, z),
+ * are taken at k = 0 and at the three smallest non-zero wave-vectors
+ * k_d = (2 pi / L) e_d, summed in binary64 in a fixed order (the same record on
+ * every run).  One record is HSG_FOURIER_VALUES doubles:
+ *     [0, 9)               Q^{mu nu}(0), row-major (= hsg_overlap's first 9 values)
+ *     [9 + 18d, 18 + 18d)  Re Q^{mu nu}(k_d), d = 0, 1, 2 for x, y, z
+ *     [18 + 18d, 27 + 18d) Im Q^{mu nu}(k_d)
+ *     [63]                 q2(0) = sum_{mu nu} Q^{mu nu}(0)^2
+ *     [64]                 q2(k_min) = (1/3) sum_d sum_{mu nu} |Q^{mu nu}(k_d)|^2
+ * Over a series of records (thermal history, disorder samples), chi_SG(k) = N <q2(k)>,
+ * the second-moment correlation length is sqrt(chi_SG(0)/chi_SG(k_min) - 1) /
+ * (2 sin(pi/L)) and the Binder cumulant of the 9-component order parameter is
+ * (11 - 9 <q2(0)^2> / <q2(0)>^2) / 2. */
+#define HSG_FOURIER_VALUES 65
+
+/* The record of lattices a and b into out_dev (device, HSG_FOURIER_VALUES doubles).
+ * HSG_EINVAL if L or dtype differ or out_dev is NULL; a's work buffer is used as
+ * scratch. */
+int hsg_overlap_fourier(const hsg_lattice *a, const hsg_lattice *b, double *out_dev,
+                        void *stream);
+
 /* ======================================================================================
  * Batched form: many independent lattices ("chains") -- disorder samples, replicas and
  * temperatures -- advanced by one launch.  Each workgroup owns one chain and runs its
@@ -201,6 +226,12 @@ int hsg_batch_energy(const hsg_batch *b, double *out_dev, void *stream);
 int hsg_batch_overlap(const hsg_batch *b, const int32_t *pairs_dev, int32_t n_pairs,
                       double *out_dev, void *stream);
 
+/* Records of hsg_overlap_fourier for chain pairs: pairs_dev [n_pairs][2] of chain
+ * indices (device); out_dev [n_pairs][HSG_FOURIER_VALUES] (device).  A pair whose
+ * indices are out of range or whose chains differ in L gets a record of NaNs. */
+int hsg_batch_overlap_fourier(const hsg_batch *b, const int32_t *pairs_dev, int32_t n_pairs,
+                              double *out_dev, void *stream);
+
 /* Tiles for hsg_batch_pass_sweep: for each chain listed in active[0..n_active), its
  * colour-site range [0, L^3/2) split into runs of tile_sites (<= 1024) consecutive
  * colour sites; tiles_out[2*t] = chain, tiles_out[2*t+1] = first colour-site index.
@@ -247,6 +278,14 @@ int hsg_pt_exchange(const hsg_pt *pt, const hsg_batch *b, void *stream);
  * occupy slot t of the two ladders. */
 int hsg_pt_overlap(const hsg_pt *pt, const hsg_batch *b, const int32_t *ladder_pairs_dev,
                    int32_t n_pairs, double *out_dev, void *stream);
+
+/* Records of hsg_overlap_fourier, slot by slot, between ladders: ladder_pairs_dev
+ * [n_pairs][2] of ladder indices (device); out_dev [n_pairs][n_temps][HSG_FOURIER_VALUES]
+ * (device) for the chains in slot t of the two ladders (records of NaNs for ladder
+ * indices out of range or chains of different L).  Capturable in a HIP graph. */
+int hsg_pt_overlap_fourier(const hsg_pt *pt, const hsg_batch *b,
+                           const int32_t *ladder_pairs_dev, int32_t n_pairs, double *out_dev,
+                           void *stream);
 
 /* Message describing the last error returned to this thread ("" if none). */
 const char *hsg_last_error(void);

@@ -28,6 +28,7 @@ HSG_HEAT_BATH = 1
 HSG_SNAKE = 2
 HSG_FUSED = 4
 FUSED_MIN_L, FUSED_MAX_L = 256, 1024
+FOURIER_VALUES = 65
 L_MAX = 1290
 
 
@@ -82,9 +83,10 @@ def lib() -> ctypes.CDLL:
         L.hsg_sweep.argtypes = [LP, ctypes.POINTER(_SweepParams), I32, P]
         L.hsg_energy.argtypes = [LP, I32, P, P]
         L.hsg_overlap.argtypes = [LP, LP, P, P]
+        L.hsg_overlap_fourier.argtypes = [LP, LP, P, P]
         L.hsg_last_error.restype = ctypes.c_char_p
         for name in ("hsg_lattice_bytes", "hsg_init_lattice", "hsg_import", "hsg_export",
-                     "hsg_sweep", "hsg_energy", "hsg_overlap"):
+                     "hsg_sweep", "hsg_energy", "hsg_overlap", "hsg_overlap_fourier"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -205,6 +207,16 @@ class Lattice:
         out = torch.empty(15, dtype=torch.float64, device=self.device)
         check(lib().hsg_overlap(ctypes.byref(self._d), ctypes.byref(other._d), _ptr(out),
                                 _stream(stream)))
+        return out
+
+    def overlap_fourier(self, other: "Lattice", out: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+        """The 65-value record of hsg_overlap_fourier: Q(0) (9), Re/Im Q(k_d) for
+        d = x, y, z (18 each), q2(0), q2(k_min)."""
+        if out is None:
+            out = torch.empty(FOURIER_VALUES, dtype=torch.float64, device=self.device)
+        check(lib().hsg_overlap_fourier(ctypes.byref(self._d), ctypes.byref(other._d),
+                                        _ptr(out), _stream(stream)))
         return out
 
 

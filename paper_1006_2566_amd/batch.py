@@ -13,7 +13,8 @@ import math
 import numpy as np
 import torch
 
-from . import HSG_F32, HSG_F64, HSG_HEAT_BATH, _dtype_code, _Lattice, _ptr, _stream, check, lib
+from . import (FOURIER_VALUES, HSG_F32, HSG_F64, HSG_HEAT_BATH, _dtype_code, _Lattice, _ptr,
+               _stream, check, lib)
 
 HSG_CHAIN_INIT_J = 8
 BATCH_L_MAX = 256
@@ -56,8 +57,11 @@ def _bind():
     L.hsg_batch_overlap.argtypes = [BP, P, I32, P, P]
     L.hsg_pt_exchange.argtypes = [PP, BP, P]
     L.hsg_pt_overlap.argtypes = [PP, BP, P, I32, P, P]
+    L.hsg_batch_overlap_fourier.argtypes = [BP, P, I32, P, P]
+    L.hsg_pt_overlap_fourier.argtypes = [PP, BP, P, I32, P, P]
     for name in ("hsg_batch_check", "hsg_batch_init", "hsg_batch_sweep",
-                 "hsg_batch_energy", "hsg_batch_overlap", "hsg_pt_exchange", "hsg_pt_overlap"):
+                 "hsg_batch_energy", "hsg_batch_overlap", "hsg_pt_exchange", "hsg_pt_overlap",
+                 "hsg_batch_overlap_fourier", "hsg_pt_overlap_fourier"):
         getattr(L, name).restype = ctypes.c_int
     _bound = True
 
@@ -170,6 +174,14 @@ class Batch:
                                       _stream(stream)))
         return out
 
+    def overlap_fourier(self, pairs, stream=None) -> torch.Tensor:
+        """Records of hsg_batch_overlap_fourier, shape (n_pairs, 65)."""
+        p = torch.as_tensor(np.asarray(pairs, dtype=np.int32).reshape(-1, 2)).to(self.device)
+        out = torch.empty((p.shape[0], FOURIER_VALUES), dtype=torch.float64, device=self.device)
+        check(lib().hsg_batch_overlap_fourier(ctypes.byref(self._d), _ptr(p), p.shape[0],
+                                              _ptr(out), _stream(stream)))
+        return out
+
     def chain_offsets(self, c: int) -> tuple[int, int]:
         return int(self.table[c]["spin_offset"]), int(self.table[c]["J_offset"])
 
@@ -238,17 +250,30 @@ class Tempering:
         check(lib().hsg_pt_exchange(ctypes.byref(self._d), ctypes.byref(self.batch._d),
                                     _stream(stream)))
 
-    def overlap(self, ladder_pairs, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+    def _pairs(self, ladder_pairs) -> torch.Tensor:
         if isinstance(ladder_pairs, torch.Tensor):
-            p = ladder_pairs.to(device=self.batch.device, dtype=torch.int32).reshape(-1, 2)
-        else:
-            p = torch.as_tensor(np.asarray(ladder_pairs, dtype=np.int32).reshape(-1, 2)).to(
-                self.batch.device)
+            return ladder_pairs.to(device=self.batch.device, dtype=torch.int32).reshape(-1, 2)
+        return torch.as_tensor(np.asarray(ladder_pairs, dtype=np.int32).reshape(-1, 2)).to(
+            self.batch.device)
+
+    def overlap(self, ladder_pairs, out: torch.Tensor | None = None, stream=None) -> torch.Tensor:
+        p = self._pairs(ladder_pairs)
         if out is None:
             out = torch.empty((p.shape[0], self.n_temps, 15), dtype=torch.float64,
                               device=self.batch.device)
         check(lib().hsg_pt_overlap(ctypes.byref(self._d), ctypes.byref(self.batch._d), _ptr(p),
                                    p.shape[0], _ptr(out), _stream(stream)))
+        return out
+
+    def overlap_fourier(self, ladder_pairs, out: torch.Tensor | None = None,
+                        stream=None) -> torch.Tensor:
+        """Records of hsg_pt_overlap_fourier, shape (n_pairs, n_temps, 65)."""
+        p = self._pairs(ladder_pairs)
+        if out is None:
+            out = torch.empty((p.shape[0], self.n_temps, FOURIER_VALUES), dtype=torch.float64,
+                              device=self.batch.device)
+        check(lib().hsg_pt_overlap_fourier(ctypes.byref(self._d), ctypes.byref(self.batch._d),
+                                           _ptr(p), p.shape[0], _ptr(out), _stream(stream)))
         return out
 
 
@@ -293,13 +318,22 @@ class PTRunner:
     graph (torch.cuda.CUDAGraph) and replayed."""
 
     def __init__(self, batch: Batch, pt: Tempering, ladder_pairs, sweeps_per_exchange: int = 10,
-                 exchanges_per_measure: int = 10, use_graph: bool = True):
+                 exchanges_per_measure: int = 10, use_graph: bool = True, fourier: bool = False):
         self.batch, self.pt = batch, pt
         self.pairs = torch.as_tensor(np.asarray(ladder_pairs, dtype=np.int32).reshape(-1, 2)).to(
             batch.device)
         self.spe, self.epm = sweeps_per_exchange, exchanges_per_measure
         self.q = torch.zeros((self.pairs.shape[0], pt.n_temps, 15), dtype=torch.float64,
                              device=batch.device)
+        # with fourier=True each cycle also writes the Fourier-overlap records, and
+        # accumulate() adds them to the running moments of q2
+        self.qk = None
+        self.moments = None
+        if fourier:
+            from .observables import OverlapMoments
+            self.qk = torch.zeros((self.pairs.shape[0], pt.n_temps, FOURIER_VALUES),
+                                  dtype=torch.float64, device=batch.device)
+            self.moments = OverlapMoments((self.pairs.shape[0], pt.n_temps))
         self.use_graph = use_graph
         self.graph = None
 
@@ -308,6 +342,21 @@ class PTRunner:
             self.batch.sweep(self.spe)
             self.pt.exchange()
         self.pt.overlap(self.pairs, out=self.q)
+        if self.qk is not None:
+            self.pt.overlap_fourier(self.pairs, out=self.qk)
+
+    def accumulate(self) -> None:
+        """Adds the last cycle's Fourier records to the moments (copies them to the
+        host, so the stream is synchronised)."""
+        if self.moments is None:
+            raise ValueError("PTRunner was built without fourier=True")
+        self.moments.add(self.qk)
+
+    def L_of_pair(self) -> np.ndarray:
+        """Lattice size of each ladder pair (its first ladder's first chain)."""
+        lad = self.pt.chain_at_slot.cpu().numpy()
+        pairs = self.pairs.cpu().numpy()
+        return np.array([self.batch.specs[int(lad[a, 0])].L for a, _ in pairs])
 
     def capture(self) -> None:
         s = torch.cuda.Stream()

@@ -323,6 +323,26 @@ int hsg_overlap(const hsg_lattice* a, const hsg_lattice* b, double* out_dev, voi
                        "overlap");
 }
 
+int hsg_overlap_fourier(const hsg_lattice* a, const hsg_lattice* b, double* out_dev,
+                        void* stream) {
+  int rc = check_lattice(a);
+  if (rc) return rc;
+  rc = check_lattice(b);
+  if (rc) return rc;
+  if (a->L != b->L || a->dtype != b->dtype)
+    return fail(HSG_EINVAL, "Fourier overlap needs two lattices of the same L and dtype");
+  if (!out_dev) return fail(HSG_EINVAL, "out_dev is NULL");
+  hipStream_t st = as_stream(stream);
+  double* part = hsg::reduce_partials(a->work, a->L);
+  if (a->dtype == HSG_F32)
+    return device_status(
+        hsg::launch_overlap_fourier<float>(a->L, a->spins, b->spins, part, out_dev, st),
+        "Fourier overlap");
+  return device_status(
+      hsg::launch_overlap_fourier<double>(a->L, a->spins, b->spins, part, out_dev, st),
+      "Fourier overlap");
+}
+
 /* ------------------------------------------------------------------- batched form */
 
 int hsg_batch_check(const hsg_chain* c, int32_t n, int64_t spin_elems, int64_t J_elems) {
@@ -408,6 +428,20 @@ int hsg_batch_overlap(const hsg_batch* b, const int32_t* pairs_dev, int32_t n_pa
       "batch overlap");
 }
 
+int hsg_batch_overlap_fourier(const hsg_batch* b, const int32_t* pairs_dev, int32_t n_pairs,
+                              double* out_dev, void* stream) {
+  int rc = check_batch(b);
+  if (rc) return rc;
+  if (!pairs_dev || !out_dev || n_pairs < 0) return fail(HSG_EINVAL, "bad pairs or output");
+  if (n_pairs == 0) return HSG_OK;
+  hipStream_t st = as_stream(stream);
+  return device_status(
+      b->dtype == HSG_F32
+          ? hsg::launch_batch_overlap_fourier<float>(b, pairs_dev, n_pairs, out_dev, st)
+          : hsg::launch_batch_overlap_fourier<double>(b, pairs_dev, n_pairs, out_dev, st),
+      "batch Fourier overlap");
+}
+
 int hsg_batch_tiles(const hsg_chain* c, int32_t n_chains, const int32_t* active, int32_t n_active,
                     int32_t tile_sites, int32_t* tiles_out, int32_t capacity, int32_t* n_tiles) {
   if (!c || !active || !tiles_out || !n_tiles || n_chains < 1 || n_active < 0 || capacity < 0)
@@ -484,6 +518,23 @@ int hsg_pt_overlap(const hsg_pt* pt, const hsg_batch* b, const int32_t* ladder_p
           ? hsg::launch_pt_overlap<float>(pt, b, ladder_pairs_dev, n_pairs, out_dev, st)
           : hsg::launch_pt_overlap<double>(pt, b, ladder_pairs_dev, n_pairs, out_dev, st),
       "ladder overlap");
+}
+
+int hsg_pt_overlap_fourier(const hsg_pt* pt, const hsg_batch* b, const int32_t* ladder_pairs_dev,
+                           int32_t n_pairs, double* out_dev, void* stream) {
+  int rc = check_pt(pt);
+  if (rc) return rc;
+  rc = check_batch(b);
+  if (rc) return rc;
+  if (!ladder_pairs_dev || !out_dev || n_pairs < 0) return fail(HSG_EINVAL, "bad pairs or output");
+  if (n_pairs == 0) return HSG_OK;
+  if (pt->n_temps > 65535) return fail(HSG_EINVAL, "too many temperatures");
+  hipStream_t st = as_stream(stream);
+  return device_status(
+      b->dtype == HSG_F32
+          ? hsg::launch_pt_overlap_fourier<float>(pt, b, ladder_pairs_dev, n_pairs, out_dev, st)
+          : hsg::launch_pt_overlap_fourier<double>(pt, b, ladder_pairs_dev, n_pairs, out_dev, st),
+      "ladder Fourier overlap");
 }
 
 }  // extern "C"

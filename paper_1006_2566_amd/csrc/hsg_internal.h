@@ -25,11 +25,16 @@ Geometry pass_geometry(int32_t L);
 constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceSlots = 16;  // doubles per block partial (overlap needs 15)
+// Blocks and doubles per block partial of the Fourier-overlap reduction.
+constexpr int kFourierBlocks = 1024;
+constexpr int kFourierSlots = 64;
+constexpr int kReduceRegion = kFourierBlocks * kFourierSlots;  // doubles; >= blocks * slots
+static_assert(kReduceRegion >= kReduceBlocks * kReduceSlots, "reduce region too small");
 
 // Scratch layout of hsg_lattice.work (bytes):
 //   [0, 256)                              reserved
 //   [256, 256 + 8*n_blocks)               per-tile energy-change partials of the passes
-//   [.., + 8*kReduceBlocks*kReduceSlots)  per-block partials of energy / overlap
+//   [.., + 8*kReduceRegion)               per-block partials of energy / overlaps
 //   [fused_offset(L), + 3*N*sizeof(R))    second spin array of fused launches (only for
 //                                         L that march_supported accepts)
 size_t work_bytes_for(int32_t L);  // without the second spin array
@@ -129,6 +134,9 @@ template <typename R>
 hipError_t launch_overlap(int32_t L, const void* a, const void* b, double* partials,
                           double* out, hipStream_t stream);
 hipError_t launch_zero(double* p, int64_t n, hipStream_t stream);
+template <typename R>
+hipError_t launch_overlap_fourier(int32_t L, const void* a, const void* b, double* partials,
+                                  double* out, hipStream_t stream);
 
 }  // namespace hsg
 
@@ -150,6 +158,13 @@ template <typename R>
 hipError_t launch_pt_overlap(const hsg_pt* pt, const hsg_batch* b, const int32_t* ladder_pairs,
                              int32_t n_pairs, double* out, hipStream_t st);
 hipError_t launch_pt_exchange(const hsg_pt* pt, const hsg_batch* b, hipStream_t st);
+template <typename R>
+hipError_t launch_batch_overlap_fourier(const hsg_batch* b, const int32_t* pairs, int32_t n_pairs,
+                                        double* out, hipStream_t st);
+template <typename R>
+hipError_t launch_pt_overlap_fourier(const hsg_pt* pt, const hsg_batch* b,
+                                     const int32_t* ladder_pairs, int32_t n_pairs, double* out,
+                                     hipStream_t st);
 template <typename R>
 hipError_t launch_batch_pass_sweep(const hsg_batch* b, const int32_t* tiles, int32_t n_tiles,
                                    int32_t tile_sites, int32_t max_n_or, int32_t renorm,

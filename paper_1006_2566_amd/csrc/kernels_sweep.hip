@@ -39,8 +39,7 @@ Geometry pass_geometry(int32_t L) {
 }
 
 size_t work_bytes_for(int32_t L) {
-  return 256 + sizeof(double) * ((size_t)pass_geometry(L).n_blocks +
-                                 (size_t)kReduceBlocks * kReduceSlots);
+  return 256 + sizeof(double) * ((size_t)pass_geometry(L).n_blocks + (size_t)kReduceRegion);
 }
 
 size_t fused_offset(int32_t L) { return (work_bytes_for(L) + 255) & ~(size_t)255; }

@@ -118,6 +118,12 @@ def test_overlap_requires_matching_lattices(hsg):
     assert lib.hsg_overlap(ctypes.byref(a), ctypes.byref(b), ctypes.c_void_p(0x5000), None) == -1
     assert b"same L" in lib.hsg_last_error()
     assert lib.hsg_energy(ctypes.byref(a), 1, None, None) == -1
+    assert lib.hsg_overlap_fourier(ctypes.byref(a), ctypes.byref(b), ctypes.c_void_p(0x5000),
+                                   None) == -1
+    assert b"same L" in lib.hsg_last_error()
+    c = _desc(hsg)
+    assert lib.hsg_overlap_fourier(ctypes.byref(a), ctypes.byref(c), None, None) == -1
+    assert b"NULL" in lib.hsg_last_error()
 
 
 def test_product_path_has_no_fallback(tmp_path, monkeypatch):
