@@ -75,6 +75,8 @@ def parse():
                     help="sites per tile of the served passes (0 = autotuned)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library defaults instead of timing candidate launch shapes")
+    ap.add_argument("--no-observables", action="store_true",
+                    help="skip timing the Fourier-overlap records (chi_SG, xi inputs)")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
                          "(calibrates FETCH_SIZE / WRITE_SIZE), then 3 sweeps of the headline "
@@ -177,6 +179,35 @@ def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup, flags=0):
     t1.record(stream)
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def observables_leg(hsg, lat, torch, steps):
+    """The spin-glass observables of a replica pair at the headline size: the
+    Fourier-overlap record (hsg_overlap_fourier), HBM-bound -- both replicas' spins are
+    read once, 2 x 3 x 4 bytes per site; the rest is 63 binary64 sums per site."""
+    L = lat.L
+    other = hsg.Lattice(L, torch.float32, seed=2)
+    out = torch.empty(hsg.FOURIER_VALUES, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        lat.overlap_fourier(other, out=out)
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record(stream)
+    for _ in range(steps):
+        lat.overlap_fourier(other, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / steps
+    nbytes = 2 * 3 * 4 * L ** 3
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    rec = out.cpu().tolist()
+    return {"entry": "hsg_overlap_fourier", "L": L, "dtype": "f32",
+            "kernels": "fourier_partials_kernel<float> + fourier_finish_kernel",
+            "us_per_call": ms * 1e3, "bound": "hbm", "bytes_per_call": nbytes,
+            "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS,
+            "N_q2_0": rec[63] * L ** 3, "N_q2_kmin": rec[64] * L ** 3}
 
 
 def batched_leg(args, torch):
@@ -383,6 +414,8 @@ def main():
                                   f"{args.n_or} over-relaxation, renormalise every {R}",
                       "L": L, "k": args.k, "n_or": args.n_or, "T": args.T, "flags": flags},
            "per_k": per_k, "roofline": roofline}
+    if not args.no_observables:
+        rec["observables"] = observables_leg(hsg, lat, torch, args.steps)
     if args.batch_cycles > 0:
         del lat
         torch.cuda.empty_cache()

@@ -26,10 +26,11 @@ constexpr int kReduceBlocks = 1024;
 constexpr int kReduceThreads = 256;
 constexpr int kReduceSlots = 16;  // doubles per block partial (overlap needs 15)
 // Blocks and doubles per block partial of the Fourier-overlap reduction.
-constexpr int kFourierBlocks = 1024;
+constexpr int kFourierBlocks = 512;
 constexpr int kFourierSlots = 64;
-constexpr int kReduceRegion = kFourierBlocks * kFourierSlots;  // doubles; >= blocks * slots
-static_assert(kReduceRegion >= kReduceBlocks * kReduceSlots, "reduce region too small");
+constexpr int kReduceRegion = kReduceBlocks * kFourierSlots;  // doubles, for either reduction
+static_assert(kFourierBlocks <= kReduceBlocks && kReduceSlots <= kFourierSlots,
+              "reduce region too small");
 
 // Scratch layout of hsg_lattice.work (bytes):
 //   [0, 256)                              reserved

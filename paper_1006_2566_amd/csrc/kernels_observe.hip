@@ -8,13 +8,16 @@
 // imaginary parts of Q(k_d) (9 + 9), then q2(0) = sum |Q(0)|^2 and
 // q2(k_min) = (1/3) sum_d sum |Q(k_d)|^2.
 //
-// Every site contributes 9 products a^mu b^nu, each weighted by 1, cos and sin of
-// k_min x, k_min y and k_min z: 63 binary64 accumulators per thread, phase factors
-// from an LDS table of (cos, sin)(2 pi j / L).  The wave reduces its 63 sums with a
-// transposing butterfly (lane l ends with the total of sum l: 63 exchanges instead of
-// 63 x 6), the workgroup adds its waves in order, and the single-lattice form adds
-// the workgroups in order in a second launch, so a record is the same bit for bit on
-// every run.  The kernels are HBM-bound: 2 x 3 spin components per site.
+// Every site contributes its 9 products a^mu b^nu weighted by 1 and by cos and sin of
+// k_min x, k_min y and k_min z: 63 binary64 sums per thread.  A thread takes items of
+// four sites of one row (two for binary64 data or odd L/2) that share y and z, so
+// the y, z and k = 0 weights multiply the item's summed products once: 45 binary64
+// operations per site instead of 81, which leaves the kernel bound by HBM.  Phase
+// factors come from an LDS table of (cos, sin)(2 pi j / L).  The wave reduces its 63
+// sums with a transposing butterfly (lane l ends with the total of sum l: 63
+// exchanges instead of 63 x 6), the workgroup adds its waves in order, and the
+// single-lattice form adds the workgroups in order in a second launch, so a record is
+// the same bit for bit on every run.
 #include "hsg.h"
 #include "hsg_device.h"
 #include "hsg_internal.h"
@@ -27,34 +30,48 @@ constexpr int kFourierSums = 63;
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 
-// Position of a colour-split element e = c*Nh + xh + Lh*(y + L*z) as mixed-radix
-// digits, advanced by a fixed stride with carries (no division in the loop).
+// Work item: the sites (x, y, z) of one row (y, z) at xh = j and, when L/2 is even,
+// xh = j + L/4, in both colours -- 2H sites that share their y and z phase factors,
+// so those weights multiply the item's summed products once.  Items are numbered
+// j + (L/(2H)) * (y + L*z) and enumerated as mixed-radix digits advanced by a fixed
+// stride with carries (no division in the loop).
 struct Cursor {
-  int32_t xh, y, z, c;
+  int32_t j, y, z;
 };
 
-__device__ __forceinline__ Cursor cursor_of(int64_t e, int32_t L, int32_t Lh, int64_t Nh) {
+struct ItemShape {
+  int32_t L, Lh, Lq;  // Lq = L / (2H): items per row
+  int64_t Nh, n_items;
+};
+
+template <int H>
+__device__ __forceinline__ ItemShape item_shape(int32_t L) {
+  ItemShape sh;
+  sh.L = L;
+  sh.Lh = L / 2;
+  sh.Lq = sh.Lh / H;
+  sh.Nh = (int64_t)sh.Lh * L * L;
+  sh.n_items = (int64_t)sh.Lq * L * L;
+  return sh;
+}
+
+__device__ __forceinline__ Cursor cursor_of(int64_t w, const ItemShape& sh) {
   Cursor p;
-  p.c = (int32_t)(e / Nh);
-  const int64_t ic = e - (int64_t)p.c * Nh;
-  p.xh = (int32_t)(ic % Lh);
-  const int64_t row = ic / Lh;
-  p.y = (int32_t)(row % L);
-  p.z = (int32_t)(row / L);
+  p.j = (int32_t)(w % sh.Lq);
+  const int64_t row = w / sh.Lq;
+  p.y = (int32_t)(row % sh.L);
+  p.z = (int32_t)(row / sh.L);  // >= L once w is past the last item
   return p;
 }
 
-__device__ __forceinline__ void advance(Cursor& p, const Cursor& s, int32_t L, int32_t Lh) {
-  p.xh += s.xh;
-  int32_t carry = p.xh >= Lh;
-  p.xh -= carry ? Lh : 0;
+__device__ __forceinline__ void advance(Cursor& p, const Cursor& s, const ItemShape& sh) {
+  p.j += s.j;
+  int32_t carry = p.j >= sh.Lq;
+  p.j -= carry ? sh.Lq : 0;
   p.y += s.y + carry;
-  carry = p.y >= L;
-  p.y -= carry ? L : 0;
+  carry = p.y >= sh.L;
+  p.y -= carry ? sh.L : 0;
   p.z += s.z + carry;
-  carry = p.z >= L;
-  p.z -= carry ? L : 0;
-  p.c += s.c + carry;
 }
 
 // (cos, sin)(2 pi j / L) for j < L, filled by the workgroup.
@@ -67,48 +84,114 @@ __device__ __forceinline__ void fill_phases(double2* tab, int32_t L) {
   __syncthreads();
 }
 
-// Adds the sites e = e0, e0 + stride, ... < N of the pair (a, b) to acc.
-template <typename R>
-__device__ __forceinline__ void accumulate_sites(const R* __restrict__ a, const R* __restrict__ b,
-                                                 int32_t L, int64_t e0, int64_t stride,
-                                                 const double2* tab,
-                                                 double (&acc)[kFourierSums]) {
-  const int32_t Lh = L / 2;
-  const int64_t Nh = (int64_t)Lh * L * L, N = 2 * Nh;
-  if (e0 >= N) return;
-  Cursor p = cursor_of(e0, L, Lh, Nh);
-  const Cursor s = cursor_of(stride, L, Lh, Nh);
-  for (int64_t e = e0; e < N; e += stride) {
-    const int64_t base = e + 2 * (int64_t)p.c * Nh;  // plane 3c + mu, element ic
+// One item's inputs, fetched one item ahead of its arithmetic.
+template <typename R, int H>
+struct ItemIn {
+  R a[2 * H][3], b[2 * H][3];
+  int32_t x[2 * H];
+  int32_t y, z;
+};
+
+template <typename R, int H>
+__device__ __forceinline__ ItemIn<R, H> fetch_item(const R* __restrict__ a,
+                                                   const R* __restrict__ b, const Cursor& p,
+                                                   const ItemShape& sh) {
+  ItemIn<R, H> in;
+  const int64_t row = (int64_t)sh.Lh * (p.y + (int64_t)sh.L * p.z);
+  const int32_t par = (p.y + p.z) & 1;
+#pragma unroll
+  for (int h = 0; h < H; ++h) {
+    const int32_t xh = p.j + h * sh.Lq;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int q = 2 * h + c;
+      const int64_t base = 3 * c * sh.Nh + row + xh;  // plane 3c + mu
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        in.a[q][k] = a[base + k * sh.Nh];
+        in.b[q][k] = b[base + k * sh.Nh];
+      }
+      in.x[q] = 2 * xh + (par ^ c);
+    }
+  }
+  in.y = p.y;
+  in.z = p.z;
+  return in;
+}
+
+// acc[0..9): sum of q; acc[9 + 18d ..): sum of q cos(k_min r_d); acc[18 + 18d ..): sin.
+template <typename R, int H>
+__device__ __forceinline__ void add_item(const ItemIn<R, H>& in, const double2* tab,
+                                         double (&acc)[kFourierSums]) {
+  double P[9];  // the item's summed products, for the phases it shares
+#pragma unroll
+  for (int q = 0; q < 2 * H; ++q) {
     double av[3], bv[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      av[k] = (double)a[base + k * Nh];
-      bv[k] = (double)b[base + k * Nh];
+      av[k] = (double)in.a[q][k];
+      bv[k] = (double)in.b[q][k];
     }
-    const int32_t x = 2 * p.xh + ((p.y + p.z + p.c) & 1);
-    const double2 ph[3] = {tab[x], tab[p.y], tab[p.z]};
+    const double2 px = tab[in.x[q]];
 #pragma unroll
-    for (int nu = 0; nu < 3; ++nu) {
-      double bw[6];
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        bw[2 * d] = bv[nu] * ph[d].x;
-        bw[2 * d + 1] = bv[nu] * ph[d].y;
-      }
-#pragma unroll
-      for (int mu = 0; mu < 3; ++mu) {
-        const int m = 3 * mu + nu;
-        acc[m] = fma(av[mu], bv[nu], acc[m]);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          acc[9 + 18 * d + m] = fma(av[mu], bw[2 * d], acc[9 + 18 * d + m]);
-          acc[18 + 18 * d + m] = fma(av[mu], bw[2 * d + 1], acc[18 + 18 * d + m]);
-        }
-      }
+    for (int m = 0; m < 9; ++m) {
+      const double prod = av[m / 3] * bv[m % 3];
+      P[m] = q == 0 ? prod : P[m] + prod;
+      acc[9 + m] = fma(prod, px.x, acc[9 + m]);
+      acc[18 + m] = fma(prod, px.y, acc[18 + m]);
     }
-    advance(p, s, L, Lh);
   }
+  const double2 py = tab[in.y], pz = tab[in.z];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    acc[m] += P[m];
+    acc[27 + m] = fma(P[m], py.x, acc[27 + m]);
+    acc[36 + m] = fma(P[m], py.y, acc[36 + m]);
+    acc[45 + m] = fma(P[m], pz.x, acc[45 + m]);
+    acc[54 + m] = fma(P[m], pz.y, acc[54 + m]);
+  }
+}
+
+// Adds the items w = w0, w0 + stride, ... of the pair (a, b) to acc, in that order,
+// the loads of item i + 1 issued before the arithmetic of item i.
+template <typename R, int H>
+__device__ __forceinline__ void accumulate_items(const R* __restrict__ a,
+                                                 const R* __restrict__ b, int32_t L, int64_t w0,
+                                                 int64_t stride, const double2* tab,
+                                                 double (&acc)[kFourierSums]) {
+  const ItemShape sh = item_shape<H>(L);
+  if (w0 >= sh.n_items) return;
+  const Cursor s = cursor_of(stride, sh);
+  Cursor p = cursor_of(w0, sh);
+  ItemIn<R, H> cur = fetch_item<R, H>(a, b, p, sh);
+  for (int64_t w = w0;;) {
+    const int64_t wn = w + stride;
+    advance(p, s, sh);
+    const bool more = wn < sh.n_items;
+    ItemIn<R, H> next;
+    if (more) next = fetch_item<R, H>(a, b, p, sh);
+    add_item<R, H>(cur, tab, acc);
+    if (!more) break;
+    cur = next;
+    w = wn;
+  }
+}
+
+// Items of four sites for binary32 data where L/2 is even, of two otherwise (four
+// binary64 sites in flight twice over would not fit the register file).
+template <typename R>
+__device__ __forceinline__ bool quad_items(int32_t L) {
+  return sizeof(R) == 4 && (L / 2) % 2 == 0;
+}
+
+template <typename R>
+__device__ __forceinline__ void accumulate_pair(const R* a, const R* b, int32_t L, int64_t w0,
+                                                int64_t stride, const double2* tab,
+                                                double (&acc)[kFourierSums]) {
+  if (quad_items<R>(L))
+    accumulate_items<R, 2>(a, b, L, w0, stride, tab, acc);
+  else
+    accumulate_items<R, 1>(a, b, L, w0, stride, tab, acc);
 }
 
 // Wave totals of the 63 sums: at step o = 32, 16, ..., 1 each lane keeps the half of
@@ -177,23 +260,41 @@ __global__ __launch_bounds__(kThreads) void fourier_partials_kernel(int32_t L, c
   double acc[kFourierSums];
 #pragma unroll
   for (int k = 0; k < kFourierSums; ++k) acc[k] = 0.0;
-  accumulate_sites<R>(a, b, L, (int64_t)blockIdx.x * kThreads + threadIdx.x,
-                      (int64_t)gridDim.x * kThreads, tab, acc);
+  accumulate_pair<R>(a, b, L, (int64_t)blockIdx.x * kThreads + threadIdx.x,
+                     (int64_t)gridDim.x * kThreads, tab, acc);
   block_totals(acc, part, sums);
-  if (threadIdx.x < 64) partials[(int64_t)blockIdx.x * 64 + threadIdx.x] = sums[threadIdx.x];
+  if (threadIdx.x < 64)
+    partials[(int64_t)blockIdx.x * kFourierSlots + threadIdx.x] = sums[threadIdx.x];
 }
 
-// Second stage: workgroup partials added in order (wave w takes sums w, w + 4, ...).
-__global__ __launch_bounds__(kThreads) void fourier_finish_kernel(const double* partials,
-                                                                  int32_t nblocks, double inv_n,
-                                                                  double* out) {
+// Second stage: workgroup partials added in order.  Wave w loads the rows of blocks
+// w, w + 16, ... at once (lane = sum), then the 16 waves are added in order.
+constexpr int kFinishThreads = 1024;
+constexpr int kFinishWaves = kFinishThreads / 64;
+constexpr int kRowsPerWave = kFourierBlocks / kFinishWaves;
+
+__global__ __launch_bounds__(kFinishThreads) void fourier_finish_kernel(const double* partials,
+                                                                        int32_t nblocks,
+                                                                        double inv_n,
+                                                                        double* out) {
+  __shared__ double part[kFinishWaves * 64];
   __shared__ double sums[64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int k = wave; k < 64; k += kWaves) {
-    double t = 0.0;
-    for (int32_t i = lane; i < nblocks; i += 64) t += partials[(int64_t)i * 64 + k];
-    t = wave_sum(t);
-    if (lane == 0) sums[k] = t;
+  double v[kRowsPerWave];
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) {
+    const int32_t i = wave + r * kFinishWaves;
+    v[r] = i < nblocks ? partials[(int64_t)i * kFourierSlots + lane] : 0.0;
+  }
+  double t = 0.0;
+#pragma unroll
+  for (int r = 0; r < kRowsPerWave; ++r) t += v[r];
+  part[wave * 64 + lane] = t;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    double u = 0.0;
+    for (int w = 0; w < kFinishWaves; ++w) u += part[w * 64 + threadIdx.x];
+    sums[threadIdx.x] = u;
   }
   __syncthreads();
   write_record(sums, inv_n, out);
@@ -217,8 +318,8 @@ __device__ __forceinline__ void chain_pair_record(const hsg_chain* chains, int32
   double acc[kFourierSums];
 #pragma unroll
   for (int k = 0; k < kFourierSums; ++k) acc[k] = 0.0;
-  accumulate_sites<R>(spins + ca.spin_offset, spins + cb.spin_offset, ca.L, threadIdx.x,
-                      kThreads, tab, acc);
+  accumulate_pair<R>(spins + ca.spin_offset, spins + cb.spin_offset, ca.L, threadIdx.x,
+                     kThreads, tab, acc);
   block_totals(acc, part, sums);
   write_record(sums, 1.0 / ((double)ca.L * ca.L * ca.L), out);
 }
@@ -251,19 +352,20 @@ __global__ __launch_bounds__(kThreads) void ladder_pairs_fourier_kernel(
 
 }  // namespace
 
-static unsigned fourier_blocks(int32_t L) {
-  const int64_t N = (int64_t)L * L * L;
-  const int64_t b = (N + kThreads - 1) / kThreads;
+static unsigned fourier_blocks(int32_t L, size_t elem) {
+  const int64_t Lh = L / 2;
+  const int64_t items = (elem == 4 && Lh % 2 == 0 ? Lh / 2 : Lh) * L * L;
+  const int64_t b = (items + kThreads - 1) / kThreads;
   return (unsigned)(b < kFourierBlocks ? b : kFourierBlocks);
 }
 
 template <typename R>
 hipError_t launch_overlap_fourier(int32_t L, const void* a, const void* b, double* partials,
                                   double* out, hipStream_t stream) {
-  const unsigned nb = fourier_blocks(L);
+  const unsigned nb = fourier_blocks(L, sizeof(R));
   hipLaunchKernelGGL(fourier_partials_kernel<R>, dim3(nb), dim3(kThreads), 0, stream, L,
                      (const R*)a, (const R*)b, partials);
-  hipLaunchKernelGGL(fourier_finish_kernel, dim3(1), dim3(kThreads), 0, stream,
+  hipLaunchKernelGGL(fourier_finish_kernel, dim3(1), dim3(kFinishThreads), 0, stream,
                      (const double*)partials, (int32_t)nb, 1.0 / ((double)L * L * L), out);
   return hipGetLastError();
 }
