@@ -52,9 +52,9 @@ extern "C" {
 
 #define HSG_L_MAX 1290 /* largest L: N = L^3 < 2^31 keeps every site index in 32 bits */
 
-/* Sweep flags (hsg_sweep_params.flags).  HSG_SNAKE and HSG_FUSED change the order in
- * which memory is touched, never a spin; with HSG_FUSED the binary64 energy changes are
- * summed in another (still fixed) order. */
+/* Sweep flags (hsg_sweep_params.flags).  HSG_SNAKE, HSG_FUSED and the variants below
+ * change the order in which memory is touched, never a spin; with HSG_FUSED the binary64
+ * energy changes are summed in another (still fixed) order. */
 #define HSG_HEAT_BATH 1 /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
 #define HSG_SNAKE 2     /* successive colour passes walk the lattice in opposite z order */
 #define HSG_FUSED 4     /* run up to four consecutive colour passes per launch (binary32;
@@ -66,6 +66,23 @@ extern "C" {
                            Uses the second half of the work buffer as a second spin array */
 #define HSG_FUSED_MIN_L 256
 #define HSG_FUSED_MAX_L 1024
+/* Variants of the memory schedule that reproduce the kernel designs the paper compares
+ * (§4, Table 2: GM, TEXT, CA, SM, SM4P) on this GPU.  Each computes exactly what the
+ * default schedule (the GM analogue: one launch per colour pass reading global memory)
+ * computes, spin for spin; they exist to measure the paper's design question. */
+#define HSG_MARCH_PHASE 16  /* with HSG_FUSED: one phase -- the colour-0 and colour-1
+                               passes -- per launch of the LDS plane march (the SM
+                               analogue: three planes on chip, both colours of a plane
+                               before the next); HSG_FUSED alone, up to two phases per
+                               march in binary32, is the SM4P analogue.  HSG_EINVAL
+                               without HSG_FUSED */
+#define HSG_PLANE_LAUNCH 32 /* one launch per z slab of tiles -- per z plane for L >= 64 --
+                               instead of one per pass: 2L launches per phase, the CA
+                               analogue's launch count.  Not with HSG_FUSED */
+#define HSG_STREAM_LOADS 64 /* couplings and the other colour's spins, which a pass only
+                               reads, are loaded with the non-temporal cache hint: the
+                               nearest this GPU has to the texture path of the TEXT variant.
+                               Not with HSG_FUSED */
 
 typedef struct hsg_lattice {
   int32_t L;         /* even, 2 <= L <= HSG_L_MAX */
@@ -85,7 +102,8 @@ typedef struct hsg_sweep_params {
   int32_t n_or;         /* over-relaxation phases per sweep, >= 0; k_hits + n_or >= 1 */
   int32_t renorm_every; /* R > 0: after sweep s with (s+1) % R == 0 every spin is
                            divided by its length; 0 = never */
-  int32_t flags;        /* OR of HSG_HEAT_BATH, HSG_SNAKE and HSG_FUSED */
+  int32_t flags;        /* OR of HSG_HEAT_BATH, HSG_SNAKE, HSG_FUSED, HSG_MARCH_PHASE,
+                           HSG_PLANE_LAUNCH, HSG_STREAM_LOADS */
 } hsg_sweep_params;
 
 /* Sizes of the three device buffers of an L^3 lattice of the given dtype.  Any

@@ -27,6 +27,9 @@ HSG_F32, HSG_F64 = 0, 1
 HSG_HEAT_BATH = 1
 HSG_SNAKE = 2
 HSG_FUSED = 4
+HSG_MARCH_PHASE = 16
+HSG_PLANE_LAUNCH = 32
+HSG_STREAM_LOADS = 64
 FUSED_MIN_L, FUSED_MAX_L = 256, 1024
 FOURIER_VALUES = 65
 L_MAX = 1290

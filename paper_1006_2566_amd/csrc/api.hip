@@ -59,8 +59,14 @@ int check_params(const hsg_sweep_params* p) {
   if (p->n_or > 0x7FFF || p->k_hits > 0xFFFF)
     return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
   if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
-  if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE | HSG_FUSED))
+  if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE | HSG_FUSED | HSG_MARCH_PHASE | HSG_PLANE_LAUNCH |
+                   HSG_STREAM_LOADS))
     return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
+  if ((p->flags & HSG_MARCH_PHASE) && !(p->flags & HSG_FUSED))
+    return fail(HSG_EINVAL, "HSG_MARCH_PHASE needs HSG_FUSED");
+  if ((p->flags & HSG_FUSED) && (p->flags & (HSG_PLANE_LAUNCH | HSG_STREAM_LOADS)))
+    return fail(HSG_EINVAL, "HSG_PLANE_LAUNCH and HSG_STREAM_LOADS apply to the pass-by-pass "
+                            "schedule, not to HSG_FUSED");
   return HSG_OK;
 }
 
@@ -74,7 +80,8 @@ bool renorm_due(const hsg_sweep_params* p, uint64_t sweep) {
   return p->renorm_every > 0 && (sweep + 1) % (uint64_t)p->renorm_every == 0;
 }
 
-// Pass-by-pass schedule: one launch per colour pass over the whole lattice.
+// Pass-by-pass schedule: one launch per colour pass over the whole lattice, or with
+// HSG_PLANE_LAUNCH one launch per z slab of tiles (one z plane from L = 64 up).
 template <typename R>
 int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
   using namespace hsg;
@@ -89,8 +96,11 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   a.seed_hi = (uint32_t)(lat->seed >> 32);
   a.k_hits = p->k_hits;
   a.g = g;
+  a.nt = (p->flags & HSG_STREAM_LOADS) ? 1 : 0;
   const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
   const bool snake = (p->flags & HSG_SNAKE) != 0;
+  const bool by_slab = (p->flags & HSG_PLANE_LAUNCH) != 0;
+  const int32_t slab_tiles = g.tiles_x * g.tiles_y;
   int32_t pass_count = 0;
   for (int32_t n = 0; n < n_sweeps; ++n) {
     const uint64_t sweep = lat->sweep + (uint64_t)n;
@@ -102,9 +112,21 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
         a.colour = colour;
         a.reverse = snake ? (pass_count & 1) : 0;
         ++pass_count;
-        int rc = device_status(
-            launch_colour_pass<R>(phase == 0 ? mc : PassMode::OverRelax, a, st), "colour pass");
-        if (rc) return rc;
+        const PassMode mode = phase == 0 ? mc : PassMode::OverRelax;
+        if (!by_slab) {
+          a.tile_base = 0;
+          a.tile_count = g.n_blocks;
+          int rc = device_status(launch_colour_pass<R>(mode, a, st), "colour pass");
+          if (rc) return rc;
+          continue;
+        }
+        for (int32_t i = 0; i < g.tiles_z; ++i) {
+          const int32_t tz = a.reverse ? g.tiles_z - 1 - i : i;
+          a.tile_base = tz * slab_tiles;
+          a.tile_count = slab_tiles;
+          int rc = device_status(launch_colour_pass<R>(mode, a, st), "colour pass (slab)");
+          if (rc) return rc;
+        }
       }
     }
     if (renorm_due(p, sweep)) {
@@ -129,7 +151,7 @@ int sweep_fused(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
     return fail(HSG_EUNSUPPORTED, "fused passes: more workgroups than energy partials");
   const int32_t per = stages_per_sweep(p);
   const int64_t total = (int64_t)per * n_sweeps;
-  const int32_t smax = march_max_stages<R>();
+  const int32_t smax = (p->flags & HSG_MARCH_PHASE) ? 2 : march_max_stages<R>();
   const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
   const int32_t first_phase = p->k_hits > 0 ? 0 : 1;
   MarchArgs<R> a{};

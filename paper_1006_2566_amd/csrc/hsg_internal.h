@@ -72,7 +72,10 @@ struct PassArgs {
   uint32_t phase;
   int32_t k_hits;
   int32_t colour;
-  int32_t reverse;  // walk the tiles from the last z plane to the first
+  int32_t reverse;     // walk the tiles from the last z plane to the first
+  int32_t tile_base;   // the launch covers tiles [tile_base, tile_base + tile_count)
+  int32_t tile_count;  // (the whole pass, or one z slab of tiles)
+  int32_t nt;          // read-only data through non-temporal loads
   Geometry g;
 };
 

@@ -128,7 +128,17 @@ __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uin
 }
 
 // Updates the site in place; returns the sum of the accepted energy changes.
-template <typename R, PassMode MODE>
+// A load of data the pass only reads (couplings, the other colour's spins); with NT
+// it carries the non-temporal cache hint.
+template <bool NT, typename R>
+__device__ __forceinline__ R read_only_ld(const R* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <typename R, PassMode MODE, bool NT = false>
 __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R>& J,
                                               const SitePos& q, const HitCtx<R>& hc) {
   const int32_t L = q.L, Lh = q.Lh, c = q.c, xh = q.xh, y = q.y, z = q.z;
@@ -145,19 +155,19 @@ __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R
   const int oc = 3 * c, nc = 3 * (1 - c);
 
   // couplings of the six bonds: +x,+y,+z stored at the site, -x,-y,-z at the neighbour
-  const R j_px = J.p[oc + 0][own], j_mx = J.p[nc + 0][n_mx];
-  const R j_py = J.p[oc + 1][own], j_my = J.p[nc + 1][n_my];
-  const R j_pz = J.p[oc + 2][own], j_mz = J.p[nc + 2][n_mz];
+  const R j_px = read_only_ld<NT>(J.p[oc + 0] + own), j_mx = read_only_ld<NT>(J.p[nc + 0] + n_mx);
+  const R j_py = read_only_ld<NT>(J.p[oc + 1] + own), j_my = read_only_ld<NT>(J.p[nc + 1] + n_my);
+  const R j_pz = read_only_ld<NT>(J.p[oc + 2] + own), j_mz = read_only_ld<NT>(J.p[nc + 2] + n_mz);
   R hcomp[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const R* sn = S.p[nc + k];
-    R acc = j_px * *(sn + n_px);
-    acc = dev_fma(j_mx, *(sn + n_mx), acc);
-    acc = dev_fma(j_py, *(sn + n_py), acc);
-    acc = dev_fma(j_my, *(sn + n_my), acc);
-    acc = dev_fma(j_pz, *(sn + n_pz), acc);
-    acc = dev_fma(j_mz, *(sn + n_mz), acc);
+    R acc = j_px * read_only_ld<NT>(sn + n_px);
+    acc = dev_fma(j_mx, read_only_ld<NT>(sn + n_mx), acc);
+    acc = dev_fma(j_py, read_only_ld<NT>(sn + n_py), acc);
+    acc = dev_fma(j_my, read_only_ld<NT>(sn + n_my), acc);
+    acc = dev_fma(j_pz, read_only_ld<NT>(sn + n_pz), acc);
+    acc = dev_fma(j_mz, read_only_ld<NT>(sn + n_mz), acc);
     hcomp[k] = acc;
   }
   const Vec3<R> h{hcomp[0], hcomp[1], hcomp[2]};

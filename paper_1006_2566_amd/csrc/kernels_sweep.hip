@@ -56,6 +56,15 @@ size_t work_bytes_for(int32_t L, int32_t dtype_bytes) {
 __device__ __forceinline__ float plane_ld(const float* base, uint32_t off) {
   return *(const float*)((const char*)base + off);
 }
+// The same for data the pass only reads; with NT the load carries the non-temporal hint.
+template <bool NT>
+__device__ __forceinline__ float plane_ld_ro(const float* base, uint32_t off) {
+  const float* p = (const float*)((const char*)base + off);
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
 __device__ __forceinline__ void plane_st(float* base, uint32_t off, float v) {
   *(float*)((char*)base + off) = v;
 }
@@ -63,7 +72,7 @@ __device__ __forceinline__ void plane_st(float* base, uint32_t off, float v) {
 // The binary32 site update of the single-lattice pass: the same field (eq. 2, same
 // order of products and fused multiply-adds) and the same apply_update as update_site,
 // with 32-bit byte offsets into the six planes.
-template <PassMode MODE>
+template <PassMode MODE, bool NT>
 __device__ __forceinline__ double update_site_b32(const Planes<float>& S, const Planes<float>& J,
                                                   const SitePos& q, const HitCtx<float>& hc) {
   const uint32_t L = (uint32_t)q.L, Lh = (uint32_t)q.Lh, xh = (uint32_t)q.xh;
@@ -79,19 +88,19 @@ __device__ __forceinline__ double update_site_b32(const Planes<float>& S, const 
   const uint32_t n_py = (Lh * (yp + L * z) + xh) << 2, n_my = (Lh * (ym + L * z) + xh) << 2;
   const uint32_t n_pz = (Lh * (y + L * zp) + xh) << 2, n_mz = (Lh * (y + L * zm) + xh) << 2;
   const int oc = 3 * c, nc = 3 * (1 - c);
-  const float j_px = plane_ld(J.p[oc + 0], own), j_mx = plane_ld(J.p[nc + 0], n_mx);
-  const float j_py = plane_ld(J.p[oc + 1], own), j_my = plane_ld(J.p[nc + 1], n_my);
-  const float j_pz = plane_ld(J.p[oc + 2], own), j_mz = plane_ld(J.p[nc + 2], n_mz);
+  const float j_px = plane_ld_ro<NT>(J.p[oc + 0], own), j_mx = plane_ld_ro<NT>(J.p[nc + 0], n_mx);
+  const float j_py = plane_ld_ro<NT>(J.p[oc + 1], own), j_my = plane_ld_ro<NT>(J.p[nc + 1], n_my);
+  const float j_pz = plane_ld_ro<NT>(J.p[oc + 2], own), j_mz = plane_ld_ro<NT>(J.p[nc + 2], n_mz);
   float hcomp[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const float* sn = S.p[nc + k];
-    float acc = j_px * plane_ld(sn, n_px);
-    acc = dev_fma(j_mx, plane_ld(sn, n_mx), acc);
-    acc = dev_fma(j_py, plane_ld(sn, n_py), acc);
-    acc = dev_fma(j_my, plane_ld(sn, n_my), acc);
-    acc = dev_fma(j_pz, plane_ld(sn, n_pz), acc);
-    acc = dev_fma(j_mz, plane_ld(sn, n_mz), acc);
+    float acc = j_px * plane_ld_ro<NT>(sn, n_px);
+    acc = dev_fma(j_mx, plane_ld_ro<NT>(sn, n_mx), acc);
+    acc = dev_fma(j_py, plane_ld_ro<NT>(sn, n_py), acc);
+    acc = dev_fma(j_my, plane_ld_ro<NT>(sn, n_my), acc);
+    acc = dev_fma(j_pz, plane_ld_ro<NT>(sn, n_pz), acc);
+    acc = dev_fma(j_mz, plane_ld_ro<NT>(sn, n_mz), acc);
     hcomp[k] = acc;
   }
   const Vec3<float> h{hcomp[0], hcomp[1], hcomp[2]};
@@ -107,7 +116,7 @@ __device__ __forceinline__ double update_site_b32(const Planes<float>& S, const 
 // One tile of a colour pass (a BX x BY x BZ block of the colour's sites); Metropolis
 // and heat-bath passes add the tile's accepted energy changes to partials[tile] in a
 // fixed order (wave sums, then the waves in order).  `tile` must be wave-uniform.
-template <typename R, PassMode MODE>
+template <typename R, PassMode MODE, bool NT>
 __device__ __forceinline__ void pass_tile(const PassArgs<R>& a, int32_t tile) {
   const Geometry& g = a.g;
   const int32_t tx = tile % g.tiles_x;
@@ -128,9 +137,9 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R>& a, int32_t tile) {
   double dE_sum = 0.0;
   if (active) {
     if constexpr (sizeof(R) == 4)
-      dE_sum = update_site_b32<MODE>(a.spins, a.J, q, hc);
+      dE_sum = update_site_b32<MODE, NT>(a.spins, a.J, q, hc);
     else
-      dE_sum = update_site<R, MODE>(a.spins, a.J, q, hc);
+      dE_sum = update_site<R, MODE, NT>(a.spins, a.J, q, hc);
   }
 
   if constexpr (MODE != PassMode::OverRelax) {
@@ -142,27 +151,42 @@ __device__ __forceinline__ void pass_tile(const PassArgs<R>& a, int32_t tile) {
   }
 }
 
-template <typename R, PassMode MODE>
+// Workgroup b of the launch takes tile tile_base + xcd_tile(b) (mirrored when the pass
+// walks z backwards); the grid is tile_count workgroups.
+template <typename R, PassMode MODE, bool NT>
 __global__ __launch_bounds__(256) void colour_pass_kernel(PassArgs<R> a) {
-  int32_t tile = xcd_tile((int32_t)blockIdx.x, a.g.n_blocks);
-  if (a.reverse) tile = a.g.n_blocks - 1 - tile;
-  pass_tile<R, MODE>(a, __builtin_amdgcn_readfirstlane(tile));
+  int32_t tile = xcd_tile((int32_t)blockIdx.x, a.tile_count);
+  if (a.reverse) tile = a.tile_count - 1 - tile;
+  pass_tile<R, MODE, NT>(a, __builtin_amdgcn_readfirstlane(a.tile_base + tile));
+}
+
+template <typename R, bool NT>
+void launch_pass_kind(PassMode mode, const PassArgs<R>& a, hipStream_t stream) {
+  const dim3 grid((unsigned)a.tile_count), block(256);
+  switch (mode) {
+    case PassMode::Metropolis:
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis, NT>), grid, block, 0, stream,
+                         a);
+      break;
+    case PassMode::OverRelax:
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::OverRelax, NT>), grid, block, 0, stream,
+                         a);
+      break;
+    case PassMode::HeatBath:
+      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::HeatBath, NT>), grid, block, 0, stream,
+                         a);
+      break;
+  }
 }
 
 template <typename R>
 hipError_t launch_colour_pass(PassMode mode, const PassArgs<R>& a, hipStream_t stream) {
-  const dim3 grid((unsigned)a.g.n_blocks), block(256);
-  switch (mode) {
-    case PassMode::Metropolis:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis>), grid, block, 0, stream, a);
-      break;
-    case PassMode::OverRelax:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::OverRelax>), grid, block, 0, stream, a);
-      break;
-    case PassMode::HeatBath:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::HeatBath>), grid, block, 0, stream, a);
-      break;
-  }
+  if (a.tile_count < 1 || a.tile_base < 0 || a.tile_base + a.tile_count > a.g.n_blocks)
+    return hipErrorInvalidValue;
+  if (a.nt)
+    launch_pass_kind<R, true>(mode, a, stream);
+  else
+    launch_pass_kind<R, false>(mode, a, stream);
   return hipGetLastError();
 }
 

@@ -82,8 +82,10 @@ def test_null_and_missing_buffers_rejected(hsg):
 @pytest.mark.parametrize("T,k,n_or,R,flags,n", [
     (0.0, 1, 0, 0, 0, 1), (-1.0, 1, 0, 0, 0, 1), (float("nan"), 1, 0, 0, 0, 1),
     (1.0, 0, 0, 0, 0, 1), (1.0, -1, 1, 0, 0, 1), (1.0, 1, -1, 0, 0, 1),
-    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 16, 1),
-    (1.0, 70000, 0, 0, 0, 1)])
+    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 128, 1),
+    (1.0, 70000, 0, 0, 0, 1),
+    # HSG_MARCH_PHASE without HSG_FUSED; HSG_FUSED with a pass-by-pass variant
+    (1.0, 1, 0, 0, 16, 1), (1.0, 1, 0, 0, 4 | 32, 1), (1.0, 1, 0, 0, 4 | 64, 1)])
 def test_sweep_rejects_bad_params(hsg, T, k, n_or, R, flags, n):
     lib = hsg.lib()
     d = _desc(hsg)

@@ -1,0 +1,70 @@
+"""GPU tests of the design-comparison variants (the paper's GM / TEXT / CA / SM / SM4P
+designs of §4, Table 2, as sweep flags): each computes the default schedule's spins bit
+for bit, and the pass-by-pass variants match the oracle directly."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle as O
+from tests import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def hsg():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1006_2566_amd as m
+    m.lib()
+    return m
+
+
+def variants(m):
+    return {"TEXT": m.HSG_SNAKE | m.HSG_STREAM_LOADS, "TEXT-plain": m.HSG_STREAM_LOADS,
+            "CA": m.HSG_PLANE_LAUNCH, "CA+S": m.HSG_PLANE_LAUNCH | m.HSG_SNAKE,
+            "SM": m.HSG_FUSED | m.HSG_MARCH_PHASE, "SM4P": m.HSG_FUSED}
+
+
+def run(m, L, dtype, flags, *, k, n_or, R, n, hb=False, T=0.4):
+    lat = m.Lattice(L, dtype, seed=7)
+    lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=n, heat_bath=hb, flags=flags)
+    return lat.spins.clone(), lat.energy().item()
+
+
+@pytest.mark.parametrize("L,dtype,k,n_or,R,n,hb", [
+    (64, torch.float32, 3, 1, 2, 3, False),
+    (18, torch.float64, 2, 2, 0, 2, False),
+    (256, torch.float32, 4, 1, 10, 2, False),
+    (256, torch.float32, 0, 2, 1, 2, False),
+    (256, torch.float64, 2, 1, 1, 2, True),
+])
+def test_variants_equal_default_schedule(hsg, L, dtype, k, n_or, R, n, hb):
+    ref_s, ref_E = run(hsg, L, dtype, 0, k=k, n_or=n_or, R=R, n=n, hb=hb)
+    for name, flags in variants(hsg).items():
+        if flags & hsg.HSG_FUSED and not hsg.fused_supported(L):
+            continue
+        s, E = run(hsg, L, dtype, flags, k=k, n_or=n_or, R=R, n=n, hb=hb)
+        assert torch.equal(s, ref_s), name
+        if flags & hsg.HSG_FUSED:
+            assert E == pytest.approx(ref_E, rel=1e-12), name  # summed in another order
+        else:
+            assert E == ref_E, name
+
+
+@pytest.mark.parametrize("name", ["TEXT", "CA+S"])
+def test_pass_by_pass_variants_match_oracle(hsg, name):
+    L, seed = 16, 3
+    spins, J = inputs.random_state(L, 41, np.float32)
+    lat = hsg.Lattice(L, torch.float32, seed=seed, init=None)
+    lat.load(torch.from_numpy(spins), torch.from_numpy(J))
+    lat.sweep(T=0.5, k=3, n_or=1, renorm_every=0, n_sweeps=2, flags=variants(hsg)[name])
+    got = lat.export()[0].cpu().numpy()
+    s = spins.copy()
+    taint = np.zeros(L ** 3, dtype=np.uint8)
+    O.sweep(L, seed, s, J, T=0.5, k=3, n_or=1, n_sweeps=2, E=O.energy(L, spins, J), taint=taint)
+    ok = taint == 0
+    assert ok.sum() >= 0.99 * L ** 3
+    assert np.abs(got[:, ok] - s[:, ok]).max() <= 1e-5
