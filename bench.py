@@ -31,15 +31,23 @@ BYTES_PER_SITE_PHASE = 36.0  # binary32: read spin (12) + 3 bonds (12), write sp
 ALU_PEAK_TOPS = 157.3 / 2
 # Algorithmic 32-bit lane operations of the Metropolis pass (a fused multiply-add, a
 # compare, a select, each half of a 32x32->64 product counts one):
-#   per site: local field 3 x (1 mul + 5 fma) = 18, sigma.h 3          -> 21
-#   per hit:  Philox4x32-10 10 rounds x (2 products x 2 halves + 4 xor) = 80
-#             three uniforms 3 x (shift, or, convert, scale)            = 12
-#             trial point: 2u-1, 1-z^2, sqrt, 4u, rint, r, r^2, sin (5), cos (5),
-#             quadrant (convert, and, 4 selects), rho cos, rho sin      = 25
-#             decision: s.h (3), dE, -beta dE, exp (2), dE <= 0, u < p, or,
-#             4 selects (spin, s.h), energy sum (convert, add)          = 16
+#   per site:  local field 3 x (1 mul + 5 fma) = 18, sigma.h 3         -> 21
+#   per Philox4x32-10 block: 10 rounds x (2 products x 2 halves + 4 xor) = 80;
+#              a hit takes three of a block's four words, so k hits draw
+#              ceil(3k / 4) blocks
+#   per hit:   three uniforms 3 x (shift, or, convert, scale)           = 12
+#              trial point: 2u-1, 1-z^2, sqrt, 4u, rint, r, r^2, sin (5), cos (5),
+#              quadrant (convert, and, 4 selects), rho cos, rho sin     = 25
+#              decision: s.h (3), dE, -beta dE, exp (2), dE <= 0, u < p, or,
+#              4 selects (spin, s.h), energy sum (convert, add)         = 16
 OPS_PER_SITE = 21
-OPS_PER_HIT = 80 + 12 + 25 + 16
+OPS_PER_BLOCK = 80
+OPS_PER_HIT = 12 + 25 + 16
+
+
+def ops_per_site_pass(k: int) -> int:
+    """Algorithmic lane operations of one site's Metropolis update with k hits."""
+    return OPS_PER_SITE + OPS_PER_HIT * k + OPS_PER_BLOCK * ((3 * k + 3) // 4)
 KERNEL_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/csrc/hsg_device.h",
                   "paper_1006_2566_amd/csrc/hsg_internal.h",
                   "paper_1006_2566_amd/csrc/kernels_sweep.hip")
@@ -388,7 +396,7 @@ def main():
                              warmup=2, flags=pass_flags) / 2.0
     head = per_k[str(args.k)]
     sites_pass = N / 2
-    ops_pass = sites_pass * (OPS_PER_SITE + OPS_PER_HIT * args.k)
+    ops_pass = sites_pass * ops_per_site_pass(args.k)
     achieved = ops_pass / (ms_mh_pass * 1e-3) / 1e12
     traffic = measured_traffic() if (L == 256 and args.k == 4) else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",

@@ -14,7 +14,9 @@
  * then n_or over-relaxation phases (reflection of sigma about h, §4), each phase
  * being the colour-0 pass followed by the colour-1 pass.  Random numbers, which the
  * paper leaves aside, come from Philox4x32-10 keyed by the lattice seed with counter
- * (sweep, site, (phase << 16) | hit, stream tag).
+ * (sweep, site, (phase << 16) | block, stream tag): a site's uniforms in a phase are the
+ * words of its blocks 0, 1, ... in order, three per Metropolis hit (four hits per three
+ * blocks) and two per heat-bath draw.
  *
  * Conventions for every function:
  *  - Return HSG_OK (0) or a negative HSG_E* code; never abort, never throw.  After an

@@ -38,6 +38,18 @@ void hsgo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t o
 /* Uniform on (0,1) from a 32-bit word: ((w >> 9) + 1/2) * 2^-23, exact in binary32. */
 double hsgo_u01(uint32_t w);
 void hsgo_philox_many(int64_t n, const uint32_t *ctr, const uint32_t key[2], uint32_t *out);
+/* The Monte Carlo uniforms of one site in one phase: uniform n is hsgo_u01 of word
+   n % 4 of the Philox block with counter (sweep, site, (phase << 16) | n / 4, tag).
+   A Metropolis hit j takes uniforms 3j, 3j+1, 3j+2; a heat-bath draw j takes 2j, 2j+1. */
+typedef struct {
+  uint32_t ctr[4];
+  uint32_t key[2];
+  int64_t block; /* block held in w, -1 before the first */
+  uint32_t w[4];
+} hsgo_ustream;
+void hsgo_ustream_init(hsgo_ustream *us, uint64_t sweep, uint32_t site, uint32_t phase,
+                       uint32_t tag, const uint32_t key[2]);
+double hsgo_ustream_at(hsgo_ustream *us, int64_t n);
 void hsgo_u01_many(int64_t n, const uint32_t *w, double *out);
 /* Taylor coefficients of sin/cos(pi*r/2) in r: coef[k] = (-1)^floor(k/2) (pi/2)^k / k!,
    k = 0..17, correctly rounded from binary128 arithmetic. */

@@ -49,6 +49,27 @@ double hsgo_u01(uint32_t w) {
   return ((double)(w >> 9) * 2.0 + 1.0) * 0x1p-24;
 }
 
+void hsgo_ustream_init(hsgo_ustream *us, uint64_t sweep, uint32_t site, uint32_t phase,
+                       uint32_t tag, const uint32_t key[2]) {
+  us->ctr[0] = (uint32_t)sweep;
+  us->ctr[1] = site;
+  us->ctr[2] = phase << 16;
+  us->ctr[3] = tag;
+  us->key[0] = key[0];
+  us->key[1] = key[1];
+  us->block = -1;
+}
+
+double hsgo_ustream_at(hsgo_ustream *us, int64_t n) {
+  const int64_t b = n / 4;
+  if (b != us->block) {
+    uint32_t ctr[4] = {us->ctr[0], us->ctr[1], us->ctr[2] | (uint32_t)b, us->ctr[3]};
+    hsgo_philox4x32_10(ctr, us->key, us->w);
+    us->block = b;
+  }
+  return hsgo_u01(us->w[n % 4]);
+}
+
 /* coef[k] = (-1)^floor(k/2) * (pi/2)^k / k!: the Taylor coefficients, in the
  * reduced variable r, of cos(pi r / 2) (even k) and sin(pi r / 2) (odd k).
  * Evaluated in binary128 and rounded once to the target precision. */

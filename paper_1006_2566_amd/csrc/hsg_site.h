@@ -72,15 +72,18 @@ struct HitCtx {
 };
 
 // The update of one site given its spin s and local field h (eq. 2): reflection about
-// h (over-relaxation), or k Metropolis hits / heat-bath draws with h fixed, drawing
-// from Philox counter (sweep, site, phase << 16 | hit, tag).  s is replaced in place;
-// returns the sum of the accepted energy changes.
+// h (over-relaxation), or k Metropolis hits / heat-bath draws with h fixed.  s is
+// replaced in place; returns the sum of the accepted energy changes.
 //
-// A hit's draws, trial spin and trial energy do not depend on earlier decisions, only
-// its accept/reject step does.  With G > 1 the hits are taken G at a time: first the G
-// independent draws and trials (instruction-level parallelism for a wave with few
-// neighbours on its SIMD), then the G decisions in order.  Every operation and the
-// order of the energy sum are the same for any G.
+// Uniforms: the site's stream in a phase is the words of the Philox blocks b = 0, 1,
+// ... with counter (sweep, site, phase << 16 | b, tag), in word order.  Metropolis hit
+// j takes uniforms 3j, 3j+1, 3j+2 (polar, azimuth, acceptance), heat-bath draw j takes
+// 2j, 2j+1: four hits share three blocks, two draws one block.  The hits are taken in
+// such groups.  A hit's draws, trial spin and trial energy do not depend on earlier
+// decisions, only its accept/reject step does; with G > 1 a group's trials are formed
+// first (instruction-level parallelism for a wave with few neighbours on its SIMD),
+// then its decisions in order.  Every operation and the order of the energy sum are
+// the same for any G.
 template <typename R, PassMode MODE, int G = 1>
 __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uint32_t site,
                                                const HitCtx<R>& hc) {
@@ -88,39 +91,64 @@ __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uin
   if constexpr (MODE == PassMode::OverRelax) {
     s = reflect(s, h);
   } else {
-    const uint32_t tag = MODE == PassMode::Metropolis ? kTagMetropolis : kTagHeatBath;
+    constexpr bool kMH = MODE == PassMode::Metropolis;
+    constexpr uint32_t tag = kMH ? kTagMetropolis : kTagHeatBath;
+    constexpr int U = kMH ? 3 : 2;   // uniforms per hit
+    constexpr int H = kMH ? 4 : 2;   // hits per group
+    constexpr int NB = U * H / 4;    // Philox blocks per group
     R sh = dot3(s, h);
-    for (int32_t j0 = 0; j0 < hc.k_hits; j0 += G) {
-      Vec3<R> trial[G];
-      R th[G], u2[G];
+    uint32_t b0 = 0;
+    for (int32_t j0 = 0; j0 < hc.k_hits; j0 += H, b0 += NB) {
+      const int32_t nh = hc.k_hits - j0;  // hits left (the group takes min(H, nh))
+      uint32_t w[4 * NB];
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        if (G == 1 || j0 + g < hc.k_hits) {
-          const uint32_t j = (uint32_t)(j0 + g);
-          const Word4 w = philox10(hc.sweep, site, (hc.phase << 16) | j, tag, hc.seed_lo,
-                                   hc.seed_hi);
-          if constexpr (MODE == PassMode::Metropolis) {
-            trial[g] = sphere_point_words<R>(w.w0, w.w1);
-            u2[g] = unit_uniform<R>(w.w2);
-          } else {
-            trial[g] = heat_bath_point(h, hc.beta, unit_uniform<R>(w.w0), unit_uniform<R>(w.w1));
-          }
-          th[g] = dot3(trial[g], h);
+      for (int i = 0; i < NB; ++i) {
+        if (i == 0 || 4 * i < U * nh) {
+          const Word4 x = philox10(hc.sweep, site, (hc.phase << 16) | (b0 + (uint32_t)i), tag,
+                                   hc.seed_lo, hc.seed_hi);
+          w[4 * i] = x.w0;
+          w[4 * i + 1] = x.w1;
+          w[4 * i + 2] = x.w2;
+          w[4 * i + 3] = x.w3;
         }
       }
+      Vec3<R> trial[H];
+      R th[H], u2[H];
+      auto draw = [&](int g) {
+        if constexpr (kMH) {
+          trial[g] = sphere_point_words<R>(w[U * g], w[U * g + 1]);
+          u2[g] = unit_uniform<R>(w[U * g + 2]);
+        } else {
+          trial[g] = heat_bath_point(h, hc.beta, unit_uniform<R>(w[U * g]),
+                                     unit_uniform<R>(w[U * g + 1]));
+        }
+        th[g] = dot3(trial[g], h);
+      };
+      auto decide = [&](int g) {
+        const R dE = sh - th[g];
+        bool accept = true;
+        if constexpr (kMH) accept = (dE <= (R)0) || (u2[g] < accept_prob(-hc.beta * dE));
+        if (accept) {
+          s = trial[g];
+          sh = th[g];
+          dE_sum += (double)dE;
+        }
+      };
+      if constexpr (G == 1) {
 #pragma unroll
-      for (int g = 0; g < G; ++g) {
-        if (G == 1 || j0 + g < hc.k_hits) {
-          const R dE = sh - th[g];
-          bool accept = true;
-          if constexpr (MODE == PassMode::Metropolis)
-            accept = (dE <= (R)0) || (u2[g] < accept_prob(-hc.beta * dE));
-          if (accept) {
-            s = trial[g];
-            sh = th[g];
-            dE_sum += (double)dE;
+        for (int g = 0; g < H; ++g) {
+          if (g < nh) {
+            draw(g);
+            decide(g);
           }
         }
+      } else {
+#pragma unroll
+        for (int g = 0; g < H; ++g)
+          if (g < nh) draw(g);
+#pragma unroll
+        for (int g = 0; g < H; ++g)
+          if (g < nh) decide(g);
       }
     }
   }

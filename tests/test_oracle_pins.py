@@ -285,9 +285,12 @@ def test_k_hits_equal_field_fixed_repeats():
     c = inputs.colours(L)
     for i in np.where(c == 0)[0]:
         sig = s0[:, i].copy()
+        # the site's uniforms: the words of its Philox blocks 0, 1, ... in order, three
+        # per hit (hit 1 straddles blocks 0 and 1)
+        words = np.concatenate([O.philox([[0, i, b, O.TAG_MH]], 99)[0] for b in range(3)])
+        u_all = O.u01(words)
         for j in range(3):
-            w = O.philox([[0, i, j, O.TAG_MH]], 99)[0]
-            u = O.u01(w)
+            u = u_all[3 * j:3 * j + 3]
             t = O.trial_spin(u[0], u[1], F64)
             dE = float(sig @ h) - float(t @ h)
             if dE <= 0 or u[2] < np.exp(-dE / 1.5):
