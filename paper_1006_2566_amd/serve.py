@@ -8,6 +8,11 @@ every resident lattice, so requests that arrive while others run share the same
 launches.  A request retires when its sweeps are done; its final energy and
 magnetisation are read back and its memory is reused.
 
+The loop is pipelined: each step is enqueued before the host looks at the previous
+one, and every host<->device transfer goes through pinned memory without blocking,
+so admission, tile building and retirement of step n overlap the GPU's work on step
+n + 1 (the device never waits for the scheduler while lattices are resident).
+
 Host-side scheduling only: every sweep, energy and magnetisation is computed by
 libhsg's kernels.
 """
@@ -110,6 +115,33 @@ class Arena:
         return self.size - sum(b - a for a, b in self.free)
 
 
+class PinnedRing:
+    """Pinned host staging buffers reused in turn, each guarded by the event of the last
+    copy that used it.  Allocating pinned memory while the GPU works can stall the host
+    until the device is idle, so the server allocates all of it up front."""
+
+    def __init__(self, n_buffers: int, nbytes: int):
+        self.bufs = [torch.empty(nbytes, dtype=torch.uint8).pin_memory() for _ in range(n_buffers)]
+        self.events: list[torch.cuda.Event | None] = [None] * n_buffers
+        self.nbytes = nbytes
+        self.i = 0
+
+    def take(self) -> tuple[torch.Tensor, int]:
+        """The next buffer (waiting for its previous copy if that is still running)."""
+        k = self.i
+        self.i = (self.i + 1) % len(self.bufs)
+        if self.events[k] is not None:
+            self.events[k].synchronize()
+            self.events[k] = None
+        return self.bufs[k], k
+
+    def guard(self, k: int) -> None:
+        """Record on the current stream that buffer k is in use up to this point."""
+        ev = torch.cuda.Event()
+        ev.record()
+        self.events[k] = ev
+
+
 class Server:
     """Continuous-batching server on one GPU.
 
@@ -133,6 +165,10 @@ class Server:
         self.J = torch.zeros(per_buffer + n_slots * dummy, dtype=dtype, device=self.device)
         self.arena_s = Arena(per_buffer)
         self.arena_j = Arena(per_buffer)
+        # host staging: uploads (chain table, per-admission arrays) and read-backs
+        self._h2d = PinnedRing(64, max(n_slots * CHAIN_DTYPE.itemsize, 16 * n_slots + 64))
+        self._d2h = PinnedRing(8, 32 * n_slots + 64)
+        self._tile_ring: PinnedRing | None = None
         self.table = np.zeros(n_slots, dtype=CHAIN_DTYPE)
         for s in range(n_slots):
             self._set_dummy(s)
@@ -153,21 +189,41 @@ class Server:
         self.tiles_dev = None
         self.n_tiles = 0
         self._tiles_dirty = True
-        self.pair_buf = torch.zeros((n_slots, 2), dtype=torch.int32, device=dev)
-        self.m_buf = torch.zeros((n_slots, 15), dtype=torch.float64, device=dev)
         # where the wall time of run() goes (seconds) and how full the steps were
-        self.stats = {"steps": 0, "t_admit": 0.0, "t_step": 0.0, "t_wait": 0.0, "t_retire": 0.0,
-                      "t_idle": 0.0, "active_sum": 0, "tiles_sum": 0}
+        self.stats = {"steps": 0, "t_admit": 0.0, "t_upload": 0.0, "t_init": 0.0, "t_step": 0.0,
+                      "t_wait": 0.0, "t_retire": 0.0, "t_idle": 0.0, "active_sum": 0,
+                      "tiles_sum": 0}
 
     # ------------------------------------------------------------------ slots
     def _set_dummy(self, s: int) -> None:
         off = self.dummy_base + s * 3 * DUMMY_L ** 3
         self.table[s] = (off, off, 1, 1, DUMMY_L, 1, 0, 0, 0, 0)
 
+    @staticmethod
+    def _stage(ring: PinnedRing, arr: np.ndarray) -> tuple[torch.Tensor, int]:
+        """arr copied into the ring's next pinned buffer: (host tensor view, buffer)."""
+        a = np.ascontiguousarray(arr)
+        buf, k = ring.take()
+        view = buf[:a.nbytes]
+        view.numpy()[:] = a.reshape(-1).view(np.uint8)
+        return view.view(torch.from_numpy(a[:0]).dtype).reshape(a.shape), k
+
+    def _to_dev(self, arr: np.ndarray, ring: PinnedRing | None = None) -> torch.Tensor:
+        """Host array -> new device tensor through pinned memory, without waiting for the
+        stream."""
+        ring = ring or self._h2d
+        host, k = self._stage(ring, arr)
+        out = torch.empty(host.shape, dtype=host.dtype, device=self.device)
+        out.copy_(host, non_blocking=True)
+        ring.guard(k)
+        return out
+
     def _upload_table(self) -> None:
         check(lib().hsg_batch_check(self.table.ctypes.data_as(ctypes.c_void_p), self.n_slots,
                                     self.spins.numel(), self.J.numel()))
-        self.chains.copy_(torch.from_numpy(self.table.view(np.uint8)))
+        host, k = self._stage(self._h2d, self.table.view(np.uint8))
+        self.chains.copy_(host, non_blocking=True)
+        self._h2d.guard(k)
 
     def footprint(self, req: Request) -> int:
         return 2 * 3 * req.spins * self.es
@@ -199,7 +255,7 @@ class Server:
         sub = self.table[slots].copy()
         n = len(slots)
         dev = self.device
-        chains = torch.from_numpy(sub.view(np.uint8).copy()).to(dev)
+        chains = self._to_dev(sub.view(np.uint8))
         E = torch.zeros(n, dtype=torch.float64, device=dev)
         zeros = torch.zeros(n, dtype=torch.int32, device=dev)
         order = torch.arange(n, dtype=torch.int32, device=dev)
@@ -208,13 +264,13 @@ class Server:
                    self.J.data_ptr(), beta.data_ptr(), E.data_ptr(), zeros.data_ptr(), None,
                    order.data_ptr(), 256, 0)
         check(lib().hsg_batch_init(ctypes.byref(d), _stream(None)))
-        idx = torch.tensor(slots, dtype=torch.long, device=dev)
+        idx = self._to_dev(np.asarray(slots, dtype=np.int64))
         self.E[idx] = E
-        self.sweep_ctr[idx] = 0
+        self.sweep_ctr.index_fill_(0, idx, 0)  # (a scalar assignment would wait for the stream)
         reqs = [self.active[s][0] for s in slots]
-        self.remaining[idx] = torch.tensor([r.sweeps for r in reqs], dtype=torch.int32, device=dev)
-        self.beta[idx] = torch.tensor([0.0 if math.isinf(r.T) else 1.0 / r.T for r in reqs],
-                                      dtype=torch.float64, device=dev)
+        self.remaining[idx] = self._to_dev(np.asarray([r.sweeps for r in reqs], dtype=np.int32))
+        self.beta[idx] = self._to_dev(np.asarray([0.0 if math.isinf(r.T) else 1.0 / r.T
+                                                  for r in reqs], dtype=np.float64))
         del chains, E, zeros, order, beta  # stream-ordered frees
 
     def _build_tiles(self) -> None:
@@ -226,7 +282,11 @@ class Server:
                                     act.ctypes.data_as(ctypes.c_void_p), act.size, self.tile_sites,
                                     tiles.ctypes.data_as(ctypes.c_void_p), cap, ctypes.byref(n)))
         self.n_tiles = n.value
-        self.tiles_dev = torch.from_numpy(tiles[:2 * n.value].copy()).to(self.device)
+        # a new tensor: the previous table may still be read by a step in flight
+        need = 8 * n.value
+        if self._tile_ring is None or self._tile_ring.nbytes < need:
+            self._tile_ring = PinnedRing(4, max(need * 2, 1 << 16))
+        self.tiles_dev = self._to_dev(tiles[:2 * n.value], self._tile_ring)
         self._tiles_dirty = False
 
     def step(self) -> None:
@@ -239,35 +299,52 @@ class Server:
                                          self.n_tiles, self.tile_sites, 0, 0, self.step_sweeps,
                                          _stream(None)))
 
-    def retire(self, now_fn) -> list[Result]:
-        """Collect the lattices whose budget is spent: energy and magnetisation."""
-        rem = self.remaining.cpu().numpy()
-        done = [s for s in self.active if rem[s] == 0]
-        if not done:
-            return []
+    def _begin_retire(self, done: list[int]) -> tuple:
+        """Enqueue the read-back of finished lattices (magnetisation, tracked energy)
+        into pinned memory and free their slots and memory at once: work enqueued later
+        on the stream -- a new lattice's initial state -- runs after the read-back."""
         n = len(done)
-        pairs = torch.tensor([[s, s] for s in done], dtype=torch.int32, device=self.device)
-        self.pair_buf[:n].copy_(pairs)
-        check(lib().hsg_batch_overlap(ctypes.byref(self._d), _ptr(self.pair_buf), n,
-                                      _ptr(self.m_buf), _stream(None)))
-        m = self.m_buf[:n, 9:12].cpu().numpy()
-        E = self.E.cpu().numpy()
-        t = now_fn()
-        out = []
-        for i, s in enumerate(done):
+        pairs = self._to_dev(np.asarray([[s, s] for s in done], dtype=np.int32))
+        m_dev = torch.empty((n, 15), dtype=torch.float64, device=self.device)
+        check(lib().hsg_batch_overlap(ctypes.byref(self._d), _ptr(pairs), n, _ptr(m_dev),
+                                      _stream(None)))
+        idx = self._to_dev(np.asarray(done, dtype=np.int64))
+        buf, k = self._d2h.take()
+        both = buf[:32 * n].view(torch.float64).reshape(n, 4)  # m (3) and E per lattice
+        m_E = torch.cat([m_dev[:, 9:12], self.E[idx].unsqueeze(1)], dim=1)
+        both.copy_(m_E, non_blocking=True)
+        self._d2h.guard(k)
+        ev = self._d2h.events[k]
+        m_pin, E_pin = both[:, :3], both[:, 3]
+        info = []
+        for s in done:
             req, s_off, j_off, t_adm = self.active.pop(s)
-            out.append(Result(req.rid, float(E[s]), m[i].copy(), req.arrival, t_adm, t))
+            info.append((req, t_adm))
             self.arena_s.release(s_off, 3 * req.spins)
             self.arena_j.release(j_off, 3 * req.spins)
             self._set_dummy(s)
             self.free_slots.append(s)
         self._tiles_dirty = True
-        return out
+        self._table_dirty = True
+        return ev, info, m_pin, E_pin
+
+    @staticmethod
+    def _finish_retire(rec: tuple, t_done: float) -> list[Result]:
+        ev, info, m_pin, E_pin = rec
+        ev.synchronize()
+        m, E = m_pin.numpy().copy(), E_pin.numpy().copy()
+        return [Result(req.rid, float(E[i]), m[i].copy(), req.arrival, t_adm, t_done)
+                for i, (req, t_adm) in enumerate(info)]
 
     # -------------------------------------------------------------------- loop
     def run(self, trace: list[Request], realtime: bool = True) -> list[Result]:
         """Serve a trace.  realtime=True releases each request at its arrival time
-        (wall clock from the start of the run); False releases all at once."""
+        (wall clock from the start of the run); False releases all at once.
+
+        Each iteration: admit what fits, enqueue one step for the resident lattices and
+        a non-blocking copy of their remaining budgets, then wait for the PREVIOUS
+        step's copy and retire the lattices it shows finished (their read-back is
+        collected one iteration later)."""
         pending = deque(sorted(trace, key=lambda r: r.arrival))
         queue: deque[Request] = deque()
         results: list[Result] = []
@@ -275,7 +352,15 @@ class Server:
         now = (lambda: time.perf_counter() - t0) if realtime else (lambda: 0.0)
         st = self.stats
         clock = time.perf_counter
-        while pending or queue or self.active:
+        if not hasattr(self, "_rem_pin"):
+            self._rem_pin = [torch.empty(self.n_slots, dtype=torch.int32).pin_memory()
+                             for _ in range(2)]
+        rem_pin = self._rem_pin
+        prev = None       # (buffer, event, {slot: request id}) of the step in flight
+        retiring = []     # (record, detection time) of read-backs in flight
+        it = 0
+        self._table_dirty = False
+        while pending or queue or self.active or prev is not None or retiring:
             c0 = clock()
             t = now()
             while pending and (not realtime or pending[0].arrival <= t):
@@ -283,33 +368,56 @@ class Server:
             admitted = []
             while queue and self.try_admit(queue[0], now()):
                 admitted.append(self._slot_of(queue.popleft()))
-            if admitted:
+            ca = clock()
+            if admitted or self._table_dirty:
                 self._upload_table()
+                self._table_dirty = False
+            cb = clock()
+            if admitted:
                 self._init_new(admitted)
                 self._tiles_dirty = True
             c1 = clock()
-            st["t_admit"] += c1 - c0
-            if not self.active:
+            st["t_admit"] += ca - c0
+            st["t_upload"] += cb - ca
+            st["t_init"] += c1 - cb
+            cur = None
+            if self.active:
+                self.step()
+                b = it & 1
+                rem_pin[b].copy_(self.remaining, non_blocking=True)
+                ev = torch.cuda.Event()
+                ev.record()
+                cur = (b, ev, {s: v[0].rid for s, v in self.active.items()})
+                st["steps"] += 1
+                st["active_sum"] += len(self.active)
+                st["tiles_sum"] += self.n_tiles
+            c2 = clock()
+            st["t_step"] += c2 - c1
+            # read-backs enqueued last iteration: their step has finished by now
+            for rec, t_det in retiring:
+                results.extend(self._finish_retire(rec, t_det))
+            retiring = []
+            if prev is not None:
+                b, ev, act = prev
+                ev.synchronize()
+                c3 = clock()
+                st["t_wait"] += c3 - c2
+                t_det = now()
+                rem = rem_pin[b].numpy()
+                done = [s for s, rid in act.items()
+                        if rem[s] == 0 and s in self.active and self.active[s][0].rid == rid]
+                if done:
+                    retiring.append((self._begin_retire(done), t_det))
+                st["t_retire"] += clock() - c3
+            prev = cur
+            it += 1
+            if prev is None and not retiring and not self.active:
                 if queue:
                     raise RuntimeError(f"request {queue[0].rid} does not fit the HBM budget")
+                c4 = clock()
                 if pending and realtime:
                     time.sleep(max(0.0, pending[0].arrival - now()))
-                st["t_idle"] += clock() - c1
-                continue
-            self.step()
-            c2 = clock()
-            torch.cuda.current_stream().synchronize()
-            c3 = clock()
-            st["steps"] += 1
-            st["active_sum"] += len(self.active)
-            st["tiles_sum"] += self.n_tiles
-            finished = self.retire(now)
-            if finished:
-                self._upload_table()
-                results.extend(finished)
-            st["t_step"] += c2 - c1
-            st["t_wait"] += c3 - c2
-            st["t_retire"] += clock() - c3
+                st["t_idle"] += clock() - c4
         return results
 
     def _slot_of(self, req: Request) -> int:
