@@ -129,8 +129,8 @@ def reduce_counters(fetch_csv, write_csv):
     def is_copy(n):
         return "copy" in n.lower()
 
-    def mh(n):  # colour_pass_kernel<float, (hsg::PassMode)0>: binary32 Metropolis
-        return "colour_pass_kernel<float" in n and "PassMode)0>" in n
+    def mh(n):  # colour_pass_kernel<float, (hsg::PassMode)0, false>: binary32 Metropolis
+        return "colour_pass_kernel<float" in n and "PassMode)0, false>" in n
 
     copy_f, copy_w = pick(fetch, is_copy), pick(write, is_copy)
     mh_f, mh_w = pick(fetch, mh), pick(write, mh)

@@ -30,6 +30,10 @@ struct SmallDiv {
   __device__ __forceinline__ uint32_t div(uint32_t n) const { return d > 1 ? __umulhi(n, m) : n; }
 };
 
+// Workgroup size of the per-chain reductions (energy, overlaps): one workgroup
+// reduces a whole chain, so large chains want the largest workgroup.
+constexpr int kChainReduceThreads = 1024;
+
 template <typename R>
 struct ChainView {
   Planes<R> S, J;
@@ -183,8 +187,8 @@ __global__ __launch_bounds__(256) void batch_init_kernel(const hsg_chain* chains
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void batch_energy_kernel(const hsg_chain* chains, const R* spins,
-                                                           const R* J, double* out) {
+__global__ __launch_bounds__(kChainReduceThreads) void batch_energy_kernel(
+    const hsg_chain* chains, const R* spins, const R* J, double* out) {
   __shared__ double s_red[16];
   const hsg_chain ch = chains[blockIdx.x];
   const int32_t L = ch.L, Lh = L / 2;
@@ -228,16 +232,14 @@ __device__ __forceinline__ void pair_overlap(const hsg_chain& ca, const hsg_chai
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void chain_pairs_overlap_kernel(const hsg_chain* chains,
-                                                                  const R* spins,
-                                                                  const int32_t* pairs,
-                                                                  double* out) {
+__global__ __launch_bounds__(kChainReduceThreads) void chain_pairs_overlap_kernel(
+    const hsg_chain* chains, const R* spins, const int32_t* pairs, double* out) {
   const int32_t p = blockIdx.x;
   pair_overlap<R>(chains[pairs[2 * p]], chains[pairs[2 * p + 1]], spins, out + 15 * (int64_t)p);
 }
 
 template <typename R>
-__global__ __launch_bounds__(256) void ladder_pairs_overlap_kernel(
+__global__ __launch_bounds__(kChainReduceThreads) void ladder_pairs_overlap_kernel(
     const hsg_chain* chains, const R* spins, const int32_t* chain_at_slot, int32_t n_temps,
     const int32_t* ladder_pairs, double* out) {
   const int32_t p = blockIdx.x, t = blockIdx.y;
@@ -376,7 +378,8 @@ template <typename R>
 hipError_t launch_batch_init(const hsg_batch* b, hipStream_t st) {
   hipLaunchKernelGGL(batch_init_kernel<R>, dim3(64, (unsigned)b->n_chains), dim3(256), 0, st,
                      b->chains, (R*)b->spins, (R*)b->J);
-  hipLaunchKernelGGL(batch_energy_kernel<R>, dim3((unsigned)b->n_chains), dim3(256), 0, st,
+  hipLaunchKernelGGL(batch_energy_kernel<R>, dim3((unsigned)b->n_chains),
+                     dim3(kChainReduceThreads), 0, st,
                      b->chains, (const R*)b->spins, (const R*)b->J, b->E);
   return hipGetLastError();
 }
@@ -402,7 +405,8 @@ hipError_t launch_batch_sweep(const hsg_batch* b, int32_t n_sweeps, hipStream_t 
 
 template <typename R>
 hipError_t launch_batch_energy(const hsg_batch* b, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(batch_energy_kernel<R>, dim3((unsigned)b->n_chains), dim3(256), 0, st,
+  hipLaunchKernelGGL(batch_energy_kernel<R>, dim3((unsigned)b->n_chains),
+                     dim3(kChainReduceThreads), 0, st,
                      b->chains, (const R*)b->spins, (const R*)b->J, out);
   return hipGetLastError();
 }
@@ -410,7 +414,8 @@ hipError_t launch_batch_energy(const hsg_batch* b, double* out, hipStream_t st) 
 template <typename R>
 hipError_t launch_batch_overlap(const hsg_batch* b, const int32_t* pairs, int32_t n_pairs,
                                 double* out, hipStream_t st) {
-  hipLaunchKernelGGL(chain_pairs_overlap_kernel<R>, dim3((unsigned)n_pairs), dim3(256), 0, st,
+  hipLaunchKernelGGL(chain_pairs_overlap_kernel<R>, dim3((unsigned)n_pairs),
+                     dim3(kChainReduceThreads), 0, st,
                      b->chains, (const R*)b->spins, pairs, out);
   return hipGetLastError();
 }
@@ -419,7 +424,8 @@ template <typename R>
 hipError_t launch_pt_overlap(const hsg_pt* pt, const hsg_batch* b, const int32_t* ladder_pairs,
                              int32_t n_pairs, double* out, hipStream_t st) {
   hipLaunchKernelGGL(ladder_pairs_overlap_kernel<R>, dim3((unsigned)n_pairs, (unsigned)pt->n_temps),
-                     dim3(256), 0, st, b->chains, (const R*)b->spins, pt->chain_at_slot,
+                     dim3(kChainReduceThreads), 0, st, b->chains, (const R*)b->spins,
+                     pt->chain_at_slot,
                      pt->n_temps, ladder_pairs, out);
   return hipGetLastError();
 }
