@@ -389,7 +389,7 @@ def main():
     # average duration: Metropolis-only sweeps (two passes each, one energy fold per
     # call) timed with events on the launch stream.  The over-relaxation pass, bound
     # by HBM, is timed the same way.
-    pass_flags = flags & ~hsg.HSG_FUSED  # one launch per colour pass
+    pass_flags = flags & ~(hsg.HSG_FUSED | hsg.HSG_PHASE_LAUNCH)  # one launch per colour pass
     ms_mh_pass = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=args.steps,
                              warmup=2, flags=pass_flags) / 2.0
     ms_or_pass = time_sweeps(lat, torch, T=args.T, k=0, n_or=1, R=0, steps=args.steps,

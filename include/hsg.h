@@ -81,6 +81,11 @@ extern "C" {
 #define HSG_PLANE_LAUNCH 32 /* one launch per z slab of tiles -- per z plane for L >= 64 --
                                instead of one per pass: 2L launches per phase, the CA
                                analogue's launch count.  Not with HSG_FUSED */
+#define HSG_PHASE_LAUNCH 128 /* each over-relaxation phase -- its colour-0 and colour-1
+                               passes -- runs as one launch that marches through z with a
+                               window of planes in LDS, reading and writing the spins once
+                               (L a multiple of 64, L >= 64; else ignored).  Uses the second
+                               spin array of the work buffer.  Not with HSG_FUSED */
 #define HSG_STREAM_LOADS 64 /* couplings and the other colour's spins, which a pass only
                                reads, are loaded with the non-temporal cache hint: the
                                nearest this GPU has to the texture path of the TEXT variant.

@@ -30,6 +30,7 @@ HSG_FUSED = 4
 HSG_MARCH_PHASE = 16
 HSG_PLANE_LAUNCH = 32
 HSG_STREAM_LOADS = 64
+HSG_PHASE_LAUNCH = 128
 FUSED_MIN_L, FUSED_MAX_L = 256, 1024
 FOURIER_VALUES = 65
 L_MAX = 1290
@@ -38,6 +39,11 @@ L_MAX = 1290
 def fused_supported(L: int) -> bool:
     """Whether HSG_FUSED takes effect for an L^3 lattice."""
     return FUSED_MIN_L <= L <= FUSED_MAX_L and L % 64 == 0
+
+
+def phase_supported(L: int) -> bool:
+    """Whether HSG_PHASE_LAUNCH takes effect for an L^3 lattice (L a multiple of 64)."""
+    return L >= 64 and L % 64 == 0
 
 
 def default_flags(L: int) -> int:

@@ -14,6 +14,9 @@ sweep flags, and every analogue computes exactly the default schedule's spins:
     CA    HSG_PLANE_LAUNCH                   one launch per z plane (2L per phase)
     SM    HSG_FUSED | HSG_MARCH_PHASE        LDS plane march, one phase (2 passes) per launch
     SM4P  HSG_FUSED                          LDS plane march, up to four passes per launch
+    PH    HSG_SNAKE | HSG_PHASE_LAUNCH       each over-relaxation phase as one launch (a
+                                             lean one-phase LDS march; Metropolis phases
+                                             pass by pass as in GM+S)
 
 The march needs 256 <= L <= 1024 (L a multiple of 64); elsewhere SM and SM4P are
 reported as unsupported.  Workloads: over-relaxation only (the paper's Table 2) and
@@ -30,8 +33,8 @@ import json
 
 import torch
 
-from . import (HSG_FUSED, HSG_MARCH_PHASE, HSG_PLANE_LAUNCH, HSG_SNAKE, HSG_STREAM_LOADS,
-               Lattice, fused_supported)
+from . import (HSG_FUSED, HSG_MARCH_PHASE, HSG_PHASE_LAUNCH, HSG_PLANE_LAUNCH, HSG_SNAKE,
+               HSG_STREAM_LOADS, Lattice, fused_supported)
 
 VARIANTS = {
     "GM": 0,
@@ -40,6 +43,7 @@ VARIANTS = {
     "CA": HSG_PLANE_LAUNCH,
     "SM": HSG_FUSED | HSG_MARCH_PHASE,
     "SM4P": HSG_FUSED,
+    "PH": HSG_SNAKE | HSG_PHASE_LAUNCH,
 }
 
 

@@ -19,7 +19,7 @@ from typing import Callable, Iterable
 
 import torch
 
-from . import HSG_FUSED, HSG_SNAKE, Lattice, fused_supported
+from . import HSG_FUSED, HSG_PHASE_LAUNCH, HSG_SNAKE, Lattice, fused_supported, phase_supported
 
 CACHE_ENV = "HSG_AUTOTUNE_CACHE"
 
@@ -91,8 +91,13 @@ def sweep_flags(L: int, dtype: torch.dtype = torch.float32, k: int = 4, n_or: in
                 heat_bath: bool = False, T: float = 0.3, renorm_every: int = 10,
                 retune: bool = False, path: str | None = None) -> int:
     """Traversal flags for hsg_sweep on an L^3 lattice: plain order, alternating z
-    order (HSG_SNAKE) or fused passes (HSG_FUSED, where the lattice allows them)."""
-    cands = [0, HSG_SNAKE] + ([HSG_FUSED] if fused_supported(L) else [])
+    order (HSG_SNAKE), over-relaxation phases in one launch each (HSG_PHASE_LAUNCH) or
+    fused passes (HSG_FUSED), where the lattice allows them."""
+    cands = [0, HSG_SNAKE]
+    if n_or > 0 and phase_supported(L):
+        cands.append(HSG_SNAKE | HSG_PHASE_LAUNCH)
+    if fused_supported(L):
+        cands.append(HSG_FUSED)
     key = f"sweep L={L} {str(dtype).replace('torch.', '')} k={k} n_or={n_or} hb={int(heat_bath)}"
 
     def measure(flags):

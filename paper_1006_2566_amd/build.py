@@ -18,7 +18,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhsg.so")
 SOURCES = ["api.hip", "kernels_sweep.hip", "kernels_lattice.hip", "kernels_batch.hip",
-           "kernels_march.hip", "kernels_observe.hip"]
+           "kernels_march.hip", "kernels_observe.hip", "kernels_phase.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HSG_OFFLOAD_ARCH", "gfx950")

@@ -60,13 +60,13 @@ int check_params(const hsg_sweep_params* p) {
     return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
   if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
   if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE | HSG_FUSED | HSG_MARCH_PHASE | HSG_PLANE_LAUNCH |
-                   HSG_STREAM_LOADS))
+                   HSG_STREAM_LOADS | HSG_PHASE_LAUNCH))
     return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
   if ((p->flags & HSG_MARCH_PHASE) && !(p->flags & HSG_FUSED))
     return fail(HSG_EINVAL, "HSG_MARCH_PHASE needs HSG_FUSED");
-  if ((p->flags & HSG_FUSED) && (p->flags & (HSG_PLANE_LAUNCH | HSG_STREAM_LOADS)))
-    return fail(HSG_EINVAL, "HSG_PLANE_LAUNCH and HSG_STREAM_LOADS apply to the pass-by-pass "
-                            "schedule, not to HSG_FUSED");
+  if ((p->flags & HSG_FUSED) && (p->flags & (HSG_PLANE_LAUNCH | HSG_STREAM_LOADS | HSG_PHASE_LAUNCH)))
+    return fail(HSG_EINVAL, "HSG_PLANE_LAUNCH, HSG_STREAM_LOADS and HSG_PHASE_LAUNCH apply to the "
+                            "pass-by-pass schedule, not to HSG_FUSED");
   return HSG_OK;
 }
 
@@ -88,7 +88,18 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   const Geometry g = pass_geometry(lat->L);
   const int64_t Nh = (int64_t)lat->L * lat->L * lat->L / 2;
   PassArgs<R> a{};
-  a.spins = planes_of<R>(lat->spins, Nh);
+  R* bufs[2] = {(R*)lat->spins, (R*)((char*)lat->work + fused_offset(lat->L))};
+  int cur = 0;  // buffer holding the current spins (phase launches flip it)
+  const bool phase_launch = (p->flags & HSG_PHASE_LAUNCH) && phase_supported(lat->L);
+  PhaseArgs<R> ph{};
+  ph.J = (const R*)lat->J;
+  ph.partials = pass_partials(lat->work);
+  ph.beta = (R)(1.0 / p->T);
+  ph.seed_lo = (uint32_t)lat->seed;
+  ph.seed_hi = (uint32_t)(lat->seed >> 32);
+  ph.k_hits = p->k_hits;
+  ph.L = lat->L;
+  a.spins = planes_of<R>(bufs[cur], Nh);
   a.J = planes_of<R>(lat->J, Nh);
   a.partials = pass_partials(lat->work);
   a.beta = (R)(1.0 / p->T);
@@ -108,6 +119,18 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
     for (int32_t phase = 0; phase <= p->n_or; ++phase) {
       if (phase == 0 && p->k_hits == 0) continue;
       a.phase = (uint32_t)phase;
+      if (phase_launch && phase > 0) {
+        ph.in = bufs[cur];
+        ph.out = bufs[1 - cur];
+        ph.sweep = (uint32_t)sweep;
+        ph.phase = (uint32_t)phase;
+        int rc = device_status(launch_phase<R>(ph, PassMode::OverRelax, st), "phase launch");
+        if (rc) return rc;
+        cur = 1 - cur;
+        a.spins = planes_of<R>(bufs[cur], Nh);
+        pass_count += 2;
+        continue;
+      }
       for (int32_t colour = 0; colour < 2; ++colour) {
         a.colour = colour;
         a.reverse = snake ? (pass_count & 1) : 0;
@@ -130,9 +153,15 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
       }
     }
     if (renorm_due(p, sweep)) {
-      int rc = device_status(launch_renormalise<R>(lat->L, lat->spins, 2, st), "renormalise");
+      int rc = device_status(launch_renormalise<R>(lat->L, bufs[cur], 2, st), "renormalise");
       if (rc) return rc;
     }
+  }
+  if (cur != 0) {
+    const size_t bytes = (size_t)3 * lat->L * lat->L * lat->L * sizeof(R);
+    int rc = device_status(hipMemcpyAsync(bufs[0], bufs[1], bytes, hipMemcpyDeviceToDevice, st),
+                           "copy spins");
+    if (rc) return rc;
   }
   return HSG_OK;
 }
@@ -306,6 +335,10 @@ int hsg_sweep(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, voi
   const size_t elem = lat->dtype == HSG_F32 ? 4 : 8;
   if (use_fused(lat, p) && lat->work_bytes < hsg::work_bytes_for(lat->L, (int32_t)elem))
     return fail(HSG_EINVAL, "HSG_FUSED needs a work buffer of %zu bytes (has %zu)",
+                hsg::work_bytes_for(lat->L, (int32_t)elem), lat->work_bytes);
+  if ((p->flags & HSG_PHASE_LAUNCH) && hsg::phase_supported(lat->L) && p->n_or > 0 &&
+      lat->work_bytes < hsg::work_bytes_for(lat->L, (int32_t)elem))
+    return fail(HSG_EINVAL, "HSG_PHASE_LAUNCH needs a work buffer of %zu bytes (has %zu)",
                 hsg::work_bytes_for(lat->L, (int32_t)elem), lat->work_bytes);
   hipStream_t st = as_stream(stream);
   rc = lat->dtype == HSG_F32 ? sweep_impl<float>(lat, p, n_sweeps, st)

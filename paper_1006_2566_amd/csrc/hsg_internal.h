@@ -36,8 +36,9 @@ static_assert(kFourierBlocks <= kReduceBlocks && kReduceSlots <= kFourierSlots,
 //   [0, 256)                              reserved
 //   [256, 256 + 8*n_blocks)               per-tile energy-change partials of the passes
 //   [.., + 8*kReduceRegion)               per-block partials of energy / overlaps
-//   [fused_offset(L), + 3*N*sizeof(R))    second spin array of fused launches (only for
-//                                         L that march_supported accepts)
+//   [fused_offset(L), + 3*N*sizeof(R))    second spin array of fused and phase launches
+//                                         (only for L that march_supported or
+//                                         phase_supported accepts)
 size_t work_bytes_for(int32_t L);  // without the second spin array
 size_t fused_offset(int32_t L);    // 256-byte aligned end of the above
 size_t work_bytes_for(int32_t L, int32_t dtype_bytes);  // with it where it applies
@@ -108,6 +109,31 @@ struct MarchArgs {
   int32_t tiles_x, tiles_y, zc;  // set by launch_march
   MarchStage st[kMarchMaxStages];
 };
+
+// One phase (colour-0 pass then colour-1 pass) in one launch.
+// (Timed on MI355X at L = 256 against 128-1024 threads, 4-32 rows, 16-64 planes.)
+constexpr int kPhaseThreads = 512;
+constexpr int kPTY = 16;  // tile rows
+constexpr int kPZ = 32;   // planes per workgroup
+constexpr int kPhaseMinL = 64;
+
+template <typename R>
+struct PhaseArgs {
+  const R* in;       // colour-split spins before the phase
+  R* out;            // after it (distinct from in)
+  const R* J;        // colour-split couplings
+  double* partials;  // one per workgroup, energy changes of its own sites are added
+  R beta;
+  uint32_t seed_lo, seed_hi;
+  uint32_t sweep, phase;
+  int32_t k_hits;
+  int32_t L;
+};
+
+bool phase_supported(int32_t L);
+int32_t phase_blocks(int32_t L);
+template <typename R>
+hipError_t launch_phase(const PhaseArgs<R>& a, PassMode mode, hipStream_t stream);
 
 bool march_supported(int32_t L);
 int32_t march_blocks(int32_t L);

@@ -45,7 +45,7 @@ size_t work_bytes_for(int32_t L) {
 size_t fused_offset(int32_t L) { return (work_bytes_for(L) + 255) & ~(size_t)255; }
 
 size_t work_bytes_for(int32_t L, int32_t dtype_bytes) {
-  if (!march_supported(L)) return work_bytes_for(L);
+  if (!march_supported(L) && !phase_supported(L)) return work_bytes_for(L);
   return fused_offset(L) + (size_t)3 * L * L * L * (size_t)dtype_bytes;
 }
 

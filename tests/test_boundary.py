@@ -82,10 +82,11 @@ def test_null_and_missing_buffers_rejected(hsg):
 @pytest.mark.parametrize("T,k,n_or,R,flags,n", [
     (0.0, 1, 0, 0, 0, 1), (-1.0, 1, 0, 0, 0, 1), (float("nan"), 1, 0, 0, 0, 1),
     (1.0, 0, 0, 0, 0, 1), (1.0, -1, 1, 0, 0, 1), (1.0, 1, -1, 0, 0, 1),
-    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 128, 1),
+    (1.0, 1, 0, -3, 0, 1), (1.0, 1, 0, 0, 8, 1), (1.0, 1, 0, 0, 0, -1), (1.0, 1, 0, 0, 512, 1),
     (1.0, 70000, 0, 0, 0, 1),
     # HSG_MARCH_PHASE without HSG_FUSED; HSG_FUSED with a pass-by-pass variant
-    (1.0, 1, 0, 0, 16, 1), (1.0, 1, 0, 0, 4 | 32, 1), (1.0, 1, 0, 0, 4 | 64, 1)])
+    (1.0, 1, 0, 0, 16, 1), (1.0, 1, 0, 0, 4 | 32, 1), (1.0, 1, 0, 0, 4 | 64, 1),
+    (1.0, 1, 0, 0, 4 | 128, 1), (1.0, 1, 0, 0, 256, 1)])
 def test_sweep_rejects_bad_params(hsg, T, k, n_or, R, flags, n):
     lib = hsg.lib()
     d = _desc(hsg)
@@ -104,6 +105,16 @@ def test_fused_needs_the_larger_work_buffer(hsg):
     assert b"HSG_FUSED" in lib.hsg_last_error()
     # lattices the fused passes do not cover need no second spin array
     assert hsg.lattice_bytes(96)[2] < 3 * 96 ** 3 * 4
+
+
+def test_phase_launch_needs_the_larger_work_buffer(hsg):
+    lib = hsg.lib()
+    full = hsg.lattice_bytes(64)[2]
+    d = _desc(hsg, L=64, work_bytes=full - 4)
+    p = hsg._SweepParams(1.0, 1, 1, 0, hsg.HSG_PHASE_LAUNCH)
+    assert lib.hsg_sweep(ctypes.byref(d), ctypes.byref(p), 1, None) == -1
+    assert b"HSG_PHASE_LAUNCH" in lib.hsg_last_error()
+    assert hsg.phase_supported(64) and not hsg.phase_supported(96)
 
 
 def test_sweep_counter_overflow_rejected(hsg):

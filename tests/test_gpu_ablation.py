@@ -25,7 +25,8 @@ def hsg():
 def variants(m):
     return {"TEXT": m.HSG_SNAKE | m.HSG_STREAM_LOADS, "TEXT-plain": m.HSG_STREAM_LOADS,
             "CA": m.HSG_PLANE_LAUNCH, "CA+S": m.HSG_PLANE_LAUNCH | m.HSG_SNAKE,
-            "SM": m.HSG_FUSED | m.HSG_MARCH_PHASE, "SM4P": m.HSG_FUSED}
+            "SM": m.HSG_FUSED | m.HSG_MARCH_PHASE, "SM4P": m.HSG_FUSED,
+            "PHASE": m.HSG_SNAKE | m.HSG_PHASE_LAUNCH, "PHASE-plain": m.HSG_PHASE_LAUNCH}
 
 
 def run(m, L, dtype, flags, *, k, n_or, R, n, hb=False, T=0.4):
@@ -36,6 +37,8 @@ def run(m, L, dtype, flags, *, k, n_or, R, n, hb=False, T=0.4):
 
 @pytest.mark.parametrize("L,dtype,k,n_or,R,n,hb", [
     (64, torch.float32, 3, 1, 2, 3, False),
+    (64, torch.float64, 0, 2, 1, 3, False),
+    (128, torch.float32, 1, 1, 0, 3, True),
     (18, torch.float64, 2, 2, 0, 2, False),
     (256, torch.float32, 4, 1, 10, 2, False),
     (256, torch.float32, 0, 2, 1, 2, False),

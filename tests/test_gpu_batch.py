@@ -239,7 +239,10 @@ def test_autotune_batch_threads_restores_state(mods, tmp_path):
 def test_autotune_sweep_flags(mods, tmp_path):
     hsg, B = mods
     from paper_1006_2566_amd import autotune as A
+    phase = hsg.HSG_SNAKE | hsg.HSG_PHASE_LAUNCH
     f = A.sweep_flags(64, k=2, n_or=1, path=str(tmp_path / "tune.json"))
-    assert f in (0, hsg.HSG_SNAKE)
+    assert f in (0, hsg.HSG_SNAKE, phase)
     f = A.sweep_flags(256, k=1, n_or=1, path=str(tmp_path / "tune.json"))
-    assert f in (0, hsg.HSG_SNAKE, hsg.HSG_FUSED)
+    assert f in (0, hsg.HSG_SNAKE, phase, hsg.HSG_FUSED)
+    f = A.sweep_flags(96, k=1, n_or=0, path=str(tmp_path / "tune.json"))
+    assert f in (0, hsg.HSG_SNAKE)
