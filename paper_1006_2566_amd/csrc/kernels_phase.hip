@@ -3,8 +3,9 @@
 // writing them once.
 //
 // Each workgroup owns a tile of 64 x kPTY sites in (x, y) and kPZ planes in z, and
-// marches through z with a window of four planes of its region (the tile widened by
-// one colour site on each side in x and by two rows in y) in LDS.  At step t it
+// marches through z holding, in LDS, three planes of each colour of its region (the
+// tile widened by one colour site on each side in x and by two rows in y): colour 1 on
+// planes a - 1 .. a + 1, colour 0 on planes a - 2 .. a.  At step t it
 // updates the colour-0 sites of plane a = z0 - 1 + t over the tile and a ring of one
 // site (stage A), then the colour-1 sites of plane a - 1 over the tile (stage B), whose
 // colour-0 neighbours on planes a - 2, a - 1 and a are then all updated.  The ring
@@ -27,10 +28,9 @@ constexpr int kPTX = 32;                 // colour sites of a tile row (64 sites
 constexpr int kRegX = kPTX + 2;          // region row: xh0 - 1 .. xh0 + 32
 constexpr int kRegY = kPTY + 4;          // region rows: y0 - 2 .. y0 + kPTY + 1
 constexpr int kColour = kRegY * kRegX;   // one colour, one component, one plane
-constexpr int kComp = 2 * kColour;       // both colours
-constexpr int kPlane = 3 * kComp;        // values of one plane of the region
-constexpr int kWin = 4;                  // planes in the window
-constexpr int kLoadRounds = (kPlane + kPhaseThreads - 1) / kPhaseThreads;
+constexpr int kSlice = 3 * kColour;      // one colour, three components, one plane
+constexpr int kRing = 3;                 // planes of each colour in LDS
+constexpr int kLoadRounds = (kSlice + kPhaseThreads - 1) / kPhaseThreads;
 constexpr int kASites = (kPTY + 2) * (kPTX + 1);  // colour-0 sites of stage A per plane
 constexpr int kARounds = (kASites + kPhaseThreads - 1) / kPhaseThreads;
 constexpr int kBSites = kPTY * kPTX;                // colour-1 sites of stage B per plane
@@ -48,52 +48,54 @@ __device__ __forceinline__ int32_t wrap_to(int32_t v, int32_t n) {
   return v < 0 ? v + n : (v >= n ? v - n : v);
 }
 
-// The region plane element e (component, colour, row, column) in the window slot and
-// in global memory (without the plane's z offset).
-template <typename R>
-struct PlaneLoad {
+// One colour of a region plane in registers: element e (component, row, column) of
+// the slice, its colour-0 global offset without the plane's z offset (colour 1 adds
+// 3 N/2).
+struct SliceOffsets {
   uint32_t off[kLoadRounds];
-  R v[kLoadRounds];
 };
 
 template <typename R>
-__device__ __forceinline__ void load_offsets(PlaneLoad<R>& pl, const PhaseCtx& m) {
+struct SliceRegs {
+  R v[kLoadRounds];
+};
+
+__device__ __forceinline__ void slice_offsets(SliceOffsets& so, const PhaseCtx& m) {
 #pragma unroll
   for (int k = 0; k < kLoadRounds; ++k) {
     const int32_t e = (int32_t)threadIdx.x + k * kPhaseThreads;
-    const int32_t comp = e / kComp;
-    const int32_t r1 = e - comp * kComp;
-    const int32_t c = r1 / kColour;
-    const int32_t r2 = r1 - c * kColour;
-    const int32_t ry = r2 / kRegX;
-    const int32_t j = r2 - ry * kRegX;
+    const int32_t comp = e / kColour;
+    const int32_t r = e - comp * kColour;
+    const int32_t ry = r / kRegX;
+    const int32_t j = r - ry * kRegX;
     const int32_t y = wrap_to(m.y0 - 2 + ry, m.L);
     const int32_t xh = wrap_to(m.xh0 - 1 + j, m.Lh);
-    pl.off[k] = (uint32_t)(3 * c + comp) * m.Nh + (uint32_t)xh + (uint32_t)m.Lh * (uint32_t)y;
+    so.off[k] = (uint32_t)comp * m.Nh + (uint32_t)xh + (uint32_t)m.Lh * (uint32_t)y;
   }
 }
 
 template <typename R>
-__device__ __forceinline__ void fetch(PlaneLoad<R>& pl, const R* in, const PhaseCtx& m,
-                                      int32_t q) {
-  const uint32_t zo = m.zstride * (uint32_t)wrap_to(q, m.L);
+__device__ __forceinline__ void fetch(SliceRegs<R>& sr, const SliceOffsets& so, const R* in,
+                                      const PhaseCtx& m, int32_t c, int32_t q) {
+  const uint32_t base = (uint32_t)(3 * c) * m.Nh + m.zstride * (uint32_t)wrap_to(q, m.L);
 #pragma unroll
   for (int k = 0; k < kLoadRounds; ++k)
-    if ((int32_t)threadIdx.x + k * kPhaseThreads < kPlane) pl.v[k] = in[pl.off[k] + zo];
+    if ((int32_t)threadIdx.x + k * kPhaseThreads < kSlice) sr.v[k] = in[so.off[k] + base];
+}
+
+// Slice of colour c, plane q (q >= -3) in the colour's ring.
+template <typename R>
+__device__ __forceinline__ R* slice(R* lds, int32_t c, int32_t q) {
+  return lds + (c * kRing + (q + 3 * kRing) % kRing) * kSlice;
 }
 
 template <typename R>
-__device__ __forceinline__ R* slot(R* lds, int32_t q) {
-  return lds + ((q % kWin + kWin) % kWin) * kPlane;
-}
-
-template <typename R>
-__device__ __forceinline__ void put(R* lds, const PlaneLoad<R>& pl, int32_t q) {
-  R* dst = slot(lds, q);
+__device__ __forceinline__ void put(R* lds, const SliceRegs<R>& sr, int32_t c, int32_t q) {
+  R* dst = slice(lds, c, q);
 #pragma unroll
   for (int k = 0; k < kLoadRounds; ++k) {
     const int32_t e = (int32_t)threadIdx.x + k * kPhaseThreads;
-    if (e < kPlane) dst[e] = pl.v[k];
+    if (e < kSlice) dst[e] = sr.v[k];
   }
 }
 
@@ -104,14 +106,13 @@ template <typename R, int C, PassMode MODE>
 __device__ __forceinline__ double phase_site(R* lds, const R* J, const PhaseCtx& m,
                                              int32_t q, int32_t z, int32_t ry, int32_t j,
                                              const HitCtx<R>& hc) {
-  const R* cur = slot(lds, q);
-  const R* up = slot(lds, q + 1);
-  const R* dn = slot(lds, q - 1);
+  const R* cur = slice(lds, 1 - C, q);
+  const R* up = slice(lds, 1 - C, q + 1);
+  const R* dn = slice(lds, 1 - C, q - 1);
   const int32_t y = wrap_to(m.y0 - 2 + ry, m.L);
   const int32_t p = (y + z + C) & 1;  // x parity of colour-C sites on this row
   const int32_t xh = wrap_to(m.xh0 - 1 + j, m.Lh);
-  constexpr int nc = (1 - C) * kColour;
-  const int32_t row = nc + ry * kRegX;
+  const int32_t row = ry * kRegX;
   const int32_t i_px = row + (p ? j + 1 : j), i_mx = row + (p ? j : j - 1);
   const int32_t i_py = row + kRegX + j, i_my = row - kRegX + j, i_z = row + j;
   // couplings: +x,+y,+z at the site (colour C planes), -x,-y,-z at the neighbours
@@ -131,7 +132,7 @@ __device__ __forceinline__ double phase_site(R* lds, const R* J, const PhaseCtx&
   R hcomp[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int32_t kb = k * kComp;
+    const int32_t kb = k * kColour;
     R acc = j_px * cur[kb + i_px];
     acc = dev_fma(j_mx, cur[kb + i_mx], acc);
     acc = dev_fma(j_py, cur[kb + i_py], acc);
@@ -141,20 +142,21 @@ __device__ __forceinline__ double phase_site(R* lds, const R* J, const PhaseCtx&
     hcomp[k] = acc;
   }
   const Vec3<R> h{hcomp[0], hcomp[1], hcomp[2]};
-  R* mine = slot(lds, q);
-  const int32_t io = C * kColour + ry * kRegX + j;
-  Vec3<R> s{mine[io], mine[kComp + io], mine[2 * kComp + io]};
+  R* mine = slice(lds, C, q);
+  const int32_t io = ry * kRegX + j;
+  Vec3<R> s{mine[io], mine[kColour + io], mine[2 * kColour + io]};
   const uint32_t site = (uint32_t)(2 * xh + p) + (uint32_t)m.L * (uint32_t)(y + m.L * z);
   const double d = apply_update<R, MODE>(s, h, site, hc);
   mine[io] = s.x;
-  mine[kComp + io] = s.y;
-  mine[2 * kComp + io] = s.z;
+  mine[kColour + io] = s.y;
+  mine[2 * kColour + io] = s.z;
   return d;
 }
 
 template <typename R, PassMode MODE>
-__global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
-  __shared__ R lds[kWin * kPlane];
+__global__ __launch_bounds__(kPhaseThreads) void
+phase_kernel(PhaseArgs<R> a) {
+  __shared__ R lds[2 * kRing * kSlice];
   __shared__ double s_red[16];
   const int32_t tiles_x = a.L / 2 / kPTX, tiles_y = a.L / kPTY;
   const int32_t tile = xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x);
@@ -171,17 +173,23 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   m.z0 = tz * kPZ;
   const HitCtx<R> hc{a.beta, a.sweep, a.phase, a.k_hits, a.seed_lo, a.seed_hi};
 
-  PlaneLoad<R> pl;
-  load_offsets<R>(pl, m);
+  // before step 0 (stage A on plane z0 - 1): colour 1 of planes z0 - 2 .. z0, colour 0
+  // of plane z0 - 1; in registers the slices the end of step 0 puts in place
+  SliceOffsets so;
+  slice_offsets(so, m);
+  SliceRegs<R> r0, r1;
   for (int32_t q = m.z0 - 2; q <= m.z0; ++q) {
-    fetch<R>(pl, a.in, m, q);
-    put<R>(lds, pl, q);
+    fetch<R>(r1, so, a.in, m, 1, q);
+    put<R>(lds, r1, 1, q);
   }
-  fetch<R>(pl, a.in, m, m.z0 + 1);
+  fetch<R>(r0, so, a.in, m, 0, m.z0 - 1);
+  put<R>(lds, r0, 0, m.z0 - 1);
+  fetch<R>(r0, so, a.in, m, 0, m.z0);
+  fetch<R>(r1, so, a.in, m, 1, m.z0 + 1);
 
   double dE = 0.0;
   for (int32_t t = 0; t <= kPZ + 1; ++t) {
-    const int32_t q = m.z0 - 1 + t;  // stage A plane
+    const int32_t q = m.z0 - 1 + t;  // stage A plane; stage B works on q - 1
     __syncthreads();
     {
       const int32_t z = wrap_to(q, m.L);
@@ -214,9 +222,13 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
         }
       }
       __syncthreads();
-      // plane b is final: write the tile's sites of both colours
-      const R* src = slot(lds, b);
-      const uint32_t zo = m.zstride * (uint32_t)z;
+    }
+    // colour 0 of plane q + 1 replaces plane q - 2 (last read by stage B)
+    if (t <= kPZ) put<R>(lds, r0, 0, q + 1);
+    if (t >= 2) {
+      // plane b = q - 1 is final: write the tile's sites of both colours
+      const int32_t b = q - 1;
+      const uint32_t zo = m.zstride * (uint32_t)wrap_to(b, m.L);
 #pragma unroll
       for (int r = 0; r < kStoreRounds; ++r) {
         const int32_t e = (int32_t)threadIdx.x + r * kPhaseThreads;
@@ -226,16 +238,20 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
           const int32_t iy = rest2 % kPTY;
           const int32_t cc = rest2 / kPTY;  // 3 * colour + component
           const int32_t c = cc / 3, comp = cc - 3 * c;
-          const R v = src[comp * kComp + c * kColour + (2 + iy) * kRegX + 1 + col];
+          const R v = slice(lds, c, b)[comp * kColour + (2 + iy) * kRegX + 1 + col];
           a.out[(uint32_t)cc * m.Nh + zo + (uint32_t)m.Lh * (uint32_t)(m.y0 + iy) +
                 (uint32_t)(m.xh0 + col)] = v;
         }
       }
+      __syncthreads();
     }
-    // the plane two ahead replaces plane q - 2 (last read by stage B above)
+    // colour 1 of plane q + 2 replaces plane q - 1 (stored above)
     if (t <= kPZ) {
-      put<R>(lds, pl, q + 2);
-      if (t + 1 <= kPZ) fetch<R>(pl, a.in, m, q + 3);
+      put<R>(lds, r1, 1, q + 2);
+      if (t + 1 <= kPZ) {
+        fetch<R>(r0, so, a.in, m, 0, q + 2);
+        fetch<R>(r1, so, a.in, m, 1, q + 3);
+      }
     }
   }
   if constexpr (MODE != PassMode::OverRelax) {
