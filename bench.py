@@ -357,7 +357,9 @@ def main():
     N = L ** 3
     if args.flags is not None:
         flags = args.flags
-    elif args.no_autotune or args.counters:
+    elif args.counters:
+        flags = hsg.HSG_SNAKE  # pass by pass: both kinds of colour pass are counted
+    elif args.no_autotune:
         flags = hsg.default_flags(L)
     else:
         from paper_1006_2566_amd import autotune

@@ -47,10 +47,11 @@ def phase_supported(L: int) -> bool:
 
 
 def default_flags(L: int) -> int:
-    """Traversal flags of a sweep that names none: pass-by-pass in alternating z order,
-    which measures faster than the fused passes on MI355X so far (HSG_FUSED is opt-in).
-    Spins are the same either way."""
-    return HSG_SNAKE
+    """Traversal flags of a sweep that names none: Monte Carlo passes one launch each in
+    alternating z order, over-relaxation phases as one launch each where the lattice
+    gives that launch enough workgroups (L >= 256), which measures fastest on MI355X
+    (HSG_FUSED is opt-in).  Spins are the same either way."""
+    return HSG_SNAKE | (HSG_PHASE_LAUNCH if L >= 256 and phase_supported(L) else 0)
 
 
 class HsgError(RuntimeError):
