@@ -83,6 +83,8 @@ def parse():
                     help="sites per tile of the served passes (0 = autotuned)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the library defaults instead of timing candidate launch shapes")
+    ap.add_argument("--no-binary64", action="store_true",
+                    help="skip timing the headline sweep with binary64 spins")
     ap.add_argument("--no-observables", action="store_true",
                     help="skip timing the Fourier-overlap records (chi_SG, xi inputs)")
     ap.add_argument("--counters", action="store_true",
@@ -187,6 +189,20 @@ def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup, flags=0):
     t1.record(stream)
     torch.cuda.synchronize()
     return t0.elapsed_time(t1) / steps
+
+
+def binary64_leg(hsg, args, torch, flags):
+    """The headline sweep with binary64 spins and couplings (the large-lattice
+    configuration compares binary32 with binary64): same L, k, n_or, T and traversal."""
+    L = args.L
+    lat = hsg.Lattice(L, torch.float64, seed=1)
+    steps = max(5, args.steps // 5)
+    ms = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=args.renorm_every,
+                     steps=steps, warmup=2, flags=flags)
+    del lat
+    torch.cuda.empty_cache()
+    return {"dtype": "f64", "steps": steps, "ms_per_step": ms,
+            "spin_updates_per_ns": L ** 3 * (args.k + args.n_or) / (ms * 1e6)}
 
 
 def observables_leg(hsg, lat, torch, steps):
@@ -434,6 +450,8 @@ def main():
                                   f"{args.n_or} over-relaxation, renormalise every {R}",
                       "L": L, "k": args.k, "n_or": args.n_or, "T": args.T, "flags": flags},
            "per_k": per_k, "roofline": roofline}
+    if not args.no_binary64:
+        rec["binary64"] = binary64_leg(hsg, args, torch, flags)
     if not args.no_observables:
         rec["observables"] = observables_leg(hsg, lat, torch, args.steps)
     if args.batch_cycles > 0:

@@ -81,7 +81,10 @@ bool renorm_due(const hsg_sweep_params* p, uint64_t sweep) {
 }
 
 // Pass-by-pass schedule: one launch per colour pass over the whole lattice, or with
-// HSG_PLANE_LAUNCH one launch per z slab of tiles (one z plane from L = 64 up).
+// HSG_PLANE_LAUNCH one launch per z slab of tiles (one z plane from L = 64 up).  With
+// HSG_PHASE_LAUNCH each over-relaxation phase is one launch reading one spin array and
+// writing the other (the lattice's and the work buffer's second one); after an odd
+// number of them the spins are copied back at the end of the call.
 template <typename R>
 int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
   using namespace hsg;
