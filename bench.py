@@ -317,12 +317,27 @@ def served_leg(args, torch):
     upd = float(sum(r.L ** 3 * r.sweeps * r.k for r in trace))
     offered = upd / trace[-1].arrival / 1e9
     st = S.latency_stats(res)
+    # the same kind of requests through the plain per-lattice path, one after another
+    # (initial state, sweeps with hsg_sweep, energy read back): the first 40 of the trace
+    import paper_1006_2566_amd as hsg
+    sample = trace[:40]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for r in sample:
+        lat = hsg.Lattice(r.L, torch.float32, seed=r.seed)
+        lat.sweep(T=r.T, k=r.k, n_or=0, n_sweeps=r.sweeps)
+        lat.energy().item()
+        del lat
+    torch.cuda.synchronize()
+    plain = sum(r.L ** 3 * r.sweeps * r.k for r in sample) / ((time.perf_counter() - t1) * 1e9)
     return {"workload": f"{len(trace)} requests, Poisson 200/s, L in {{8,16,32,64,96}}, "
                         "T in [0.1,1], sweeps log-uniform [100,1e4], k in {1,4}, binary32",
             "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
             "mean_latency_s": st["mean_s"], "wall_s": wall,
             "spin_updates_per_ns": upd / (wall * 1e9),
-            "offered_updates_per_ns": offered, "budget_mb": args.serve_budget_mb,
+            "offered_updates_per_ns": offered,
+            "plain_per_lattice_updates_per_ns": plain,
+            "speedup_vs_plain": upd / (wall * 1e9) / plain, "budget_mb": args.serve_budget_mb,
             "step_sweeps": args.serve_step, "tile_sites": tile,
             "scheduler": {k: (round(v, 3) if isinstance(v, float) else v)
                           for k, v in srv.stats.items()}}
