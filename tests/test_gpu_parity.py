@@ -193,8 +193,9 @@ def test_heat_bath_binary32_matches_oracle(hsg, L, T, k):
 @pytest.mark.parametrize("k,fused", [(1, False), (4, False), (8, False), (4, True)])
 def test_full_size_sweep_matches_oracle(hsg, k, fused):
     """L = 256 (16.8M spins), binary32, the launch configuration the benchmark
-    times (hsg_sweep's colour passes, or the fused passes): one sweep of k hits + 1
-    over-relaxation phase from a seeded state, every site compared."""
+    times (hsg_sweep's default traversal: snake-ordered Monte Carlo colour passes and
+    the over-relaxation phase as one launch; or the fused passes): one sweep of k hits
+    + 1 over-relaxation phase from a seeded state, every site compared."""
     L, seed = 256, 1
     s, J = inputs.random_state(L, 256, F32)
     lat = hsg.Lattice(L, torch.float32, seed=seed, init=None)
