@@ -96,7 +96,6 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   const bool phase_launch = (p->flags & HSG_PHASE_LAUNCH) && phase_supported(lat->L);
   PhaseArgs<R> ph{};
   ph.J = (const R*)lat->J;
-  ph.partials = pass_partials(lat->work);
   ph.beta = (R)(1.0 / p->T);
   ph.seed_lo = (uint32_t)lat->seed;
   ph.seed_hi = (uint32_t)(lat->seed >> 32);
@@ -127,7 +126,7 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
         ph.out = bufs[1 - cur];
         ph.sweep = (uint32_t)sweep;
         ph.phase = (uint32_t)phase;
-        int rc = device_status(launch_phase<R>(ph, PassMode::OverRelax, st), "phase launch");
+        int rc = device_status(launch_phase<R>(ph, st), "phase launch");
         if (rc) return rc;
         cur = 1 - cur;
         a.spins = planes_of<R>(bufs[cur], Nh);

@@ -110,8 +110,9 @@ struct MarchArgs {
   MarchStage st[kMarchMaxStages];
 };
 
-// One phase (colour-0 pass then colour-1 pass) in one launch.
-// (Timed on MI355X at L = 256 against 128-1024 threads, 4-32 rows, 16-64 planes.)
+// An over-relaxation phase (colour-0 pass then colour-1 pass) in one launch
+// (kernels_phase.hip).  Tile shape timed on MI355X at L = 256 against 128-1024
+// threads, 4-32 rows and 16-64 planes.
 constexpr int kPhaseThreads = 512;
 constexpr int kPTY = 16;  // tile rows
 constexpr int kPZ = 32;   // planes per workgroup
@@ -119,11 +120,10 @@ constexpr int kPhaseMinL = 64;
 
 template <typename R>
 struct PhaseArgs {
-  const R* in;       // colour-split spins before the phase
-  R* out;            // after it (distinct from in)
-  const R* J;        // colour-split couplings
-  double* partials;  // one per workgroup, energy changes of its own sites are added
-  R beta;
+  const R* in;  // colour-split spins before the phase
+  R* out;       // after it (distinct from in)
+  const R* J;   // colour-split couplings
+  R beta;       // (the Philox context of the site update; over-relaxation draws none)
   uint32_t seed_lo, seed_hi;
   uint32_t sweep, phase;
   int32_t k_hits;
@@ -133,7 +133,7 @@ struct PhaseArgs {
 bool phase_supported(int32_t L);
 int32_t phase_blocks(int32_t L);
 template <typename R>
-hipError_t launch_phase(const PhaseArgs<R>& a, PassMode mode, hipStream_t stream);
+hipError_t launch_phase(const PhaseArgs<R>& a, hipStream_t stream);
 
 bool march_supported(int32_t L);
 int32_t march_blocks(int32_t L);

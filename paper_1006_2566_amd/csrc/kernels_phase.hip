@@ -1,6 +1,5 @@
-// One phase of the checkerboard schedule (§4) -- the colour-0 pass and then the
-// colour-1 pass of the same update -- in one launch, reading the spins once and
-// writing them once.
+// One over-relaxation phase of the checkerboard schedule (§4) -- the colour-0 pass and
+// then the colour-1 pass -- in one launch, reading the spins once and writing them once.
 //
 // Each workgroup owns a tile of 64 x kPTY sites in (x, y) and kPZ planes in z, and
 // marches through z holding, in LDS, three planes of each colour of its region (the
@@ -15,8 +14,8 @@
 // buffer and write the tile after it to another.
 //
 // The site arithmetic (field of eq. 2 in the fixed order of the single-pass kernel,
-// then apply_update) is the single pass's, so results equal two colour passes bit for
-// bit; only the order in which binary64 energy changes are summed differs.
+// then the reflection of §4) is the single pass's, so results equal two colour passes
+// bit for bit.
 #include "hsg_device.h"
 #include "hsg_internal.h"
 #include "hsg_site.h"
@@ -153,11 +152,12 @@ __device__ __forceinline__ double phase_site(R* lds, const R* J, const PhaseCtx&
   return d;
 }
 
-template <typename R, PassMode MODE>
-__global__ __launch_bounds__(kPhaseThreads) void
-phase_kernel(PhaseArgs<R> a) {
+// The over-relaxation phase (the one the schedule runs as one launch): no energy
+// changes to record.
+template <typename R>
+__global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
+  constexpr PassMode MODE = PassMode::OverRelax;
   __shared__ R lds[2 * kRing * kSlice];
-  __shared__ double s_red[16];
   const int32_t tiles_x = a.L / 2 / kPTX, tiles_y = a.L / kPTY;
   const int32_t tile = xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x);
   const int32_t tx = tile % tiles_x;
@@ -187,13 +187,11 @@ phase_kernel(PhaseArgs<R> a) {
   fetch<R>(r0, so, a.in, m, 0, m.z0);
   fetch<R>(r1, so, a.in, m, 1, m.z0 + 1);
 
-  double dE = 0.0;
   for (int32_t t = 0; t <= kPZ + 1; ++t) {
     const int32_t q = m.z0 - 1 + t;  // stage A plane; stage B works on q - 1
     __syncthreads();
     {
       const int32_t z = wrap_to(q, m.L);
-      const bool own_plane = t >= 1 && t <= kPZ;
 #pragma unroll
       for (int r = 0; r < kARounds; ++r) {
         const int32_t i = (int32_t)threadIdx.x + r * kPhaseThreads;
@@ -203,9 +201,7 @@ phase_kernel(PhaseArgs<R> a) {
           const int32_t y = wrap_to(m.y0 - 2 + ry, m.L);
           const int32_t p0 = (y + z) & 1;
           const int32_t j = (i - dr * (kPTX + 1)) + (1 - p0);
-          const double d = phase_site<R, 0, MODE>(lds, a.J, m, q, z, ry, j, hc);
-          const int32_t x = 2 * (j - 1) + p0;  // relative to the tile's first x
-          if (own_plane && ry >= 2 && ry < 2 + kPTY && x >= 0 && x < 2 * kPTX) dE += d;
+          phase_site<R, 0, MODE>(lds, a.J, m, q, z, ry, j, hc);
         }
       }
     }
@@ -218,7 +214,7 @@ phase_kernel(PhaseArgs<R> a) {
         const int32_t i = (int32_t)threadIdx.x + r * kPhaseThreads;
         if (i < kBSites) {
           const int32_t dr = i / kPTX;
-          dE += phase_site<R, 1, MODE>(lds, a.J, m, b, z, 2 + dr, 1 + (i - dr * kPTX), hc);
+          phase_site<R, 1, MODE>(lds, a.J, m, b, z, 2 + dr, 1 + (i - dr * kPTX), hc);
         }
       }
       __syncthreads();
@@ -254,10 +250,6 @@ phase_kernel(PhaseArgs<R> a) {
       }
     }
   }
-  if constexpr (MODE != PassMode::OverRelax) {
-    const double total = block_sum(dE, s_red);
-    if (threadIdx.x == 0) a.partials[blockIdx.x] += total;
-  }
 }
 
 }  // namespace
@@ -269,24 +261,14 @@ bool phase_supported(int32_t L) {
 int32_t phase_blocks(int32_t L) { return (L / 2 / kPTX) * (L / kPTY) * (L / kPZ); }
 
 template <typename R>
-hipError_t launch_phase(const PhaseArgs<R>& a, PassMode mode, hipStream_t st) {
+hipError_t launch_phase(const PhaseArgs<R>& a, hipStream_t st) {
   if (!phase_supported(a.L)) return hipErrorInvalidValue;
   const dim3 grid((unsigned)phase_blocks(a.L)), block(kPhaseThreads);
-  switch (mode) {
-    case PassMode::Metropolis:
-      hipLaunchKernelGGL((phase_kernel<R, PassMode::Metropolis>), grid, block, 0, st, a);
-      break;
-    case PassMode::OverRelax:
-      hipLaunchKernelGGL((phase_kernel<R, PassMode::OverRelax>), grid, block, 0, st, a);
-      break;
-    case PassMode::HeatBath:
-      hipLaunchKernelGGL((phase_kernel<R, PassMode::HeatBath>), grid, block, 0, st, a);
-      break;
-  }
+  hipLaunchKernelGGL(phase_kernel<R>, grid, block, 0, st, a);
   return hipGetLastError();
 }
 
-template hipError_t launch_phase<float>(const PhaseArgs<float>&, PassMode, hipStream_t);
-template hipError_t launch_phase<double>(const PhaseArgs<double>&, PassMode, hipStream_t);
+template hipError_t launch_phase<float>(const PhaseArgs<float>&, hipStream_t);
+template hipError_t launch_phase<double>(const PhaseArgs<double>&, hipStream_t);
 
 }  // namespace hsg
