@@ -43,15 +43,38 @@ ALU_PEAK_TOPS = 157.3 / 2
 OPS_PER_SITE = 21
 OPS_PER_BLOCK = 80
 OPS_PER_HIT = 12 + 25 + 16
+# over-relaxation of a site: local field and sigma.h (21), h.h (3), 2 sigma.h / h.h (2),
+# h.h > 0 (1), reflection 3 x (fma, select) (6)
+OPS_PER_SITE_OR = 21 + 3 + 2 + 1 + 6
 
 
 def ops_per_site_pass(k: int) -> int:
     """Algorithmic lane operations of one site's Metropolis update with k hits."""
     return OPS_PER_SITE + OPS_PER_HIT * k + OPS_PER_BLOCK * ((3 * k + 3) // 4)
-KERNEL_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/csrc/hsg_device.h",
-                  "paper_1006_2566_amd/csrc/hsg_internal.h",
-                  "paper_1006_2566_amd/csrc/kernels_sweep.hip")
-TRAFFIC_FILE = "profiles/traffic_metropolis_pass_L256_f32.txt"
+_COMMON_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/csrc/hsg_device.h",
+                   "paper_1006_2566_amd/csrc/hsg_internal.h")
+# The kernels that can dominate the headline sweep: the binary32 Metropolis colour pass,
+# and the launch of the over-relaxation phase with the next sweep's colour-0 Metropolis
+# pass (HSG_PHASE_MC).  Each has its counter summary, valid while its sources are those
+# the counters were taken from.
+DOMINANT = {
+    "metropolis_pass": {
+        "kernel": "colour_pass_kernel<float, Metropolis>",
+        "trace_name": "colour_pass_kernel<float, (hsg::PassMode)0, false>",
+        "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_sweep.hip",),
+        "traffic_file": "profiles/traffic_metropolis_pass_L256_f32.txt",
+        "title": "one Metropolis colour pass",
+        "sites": 0.5,  # updated sites per launch, in units of N
+    },
+    "phase_mc": {
+        "kernel": "phase_kernel<float, 3, Metropolis>",
+        "trace_name": "phase_kernel<float, 3, (hsg::PassMode)0>",
+        "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_phase.hip",),
+        "traffic_file": "profiles/traffic_phase_mc_L256_f32.txt",
+        "title": "one over-relaxation phase with the next colour-0 Metropolis pass",
+        "sites": 1.0,  # the phase's compulsory traffic: every site read and written once
+    },
+}
 
 
 def parse():
@@ -93,16 +116,17 @@ def parse():
                          "configuration; prints no JSON")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="turn the counter_collection.csv files of a FETCH_SIZE and a "
-                         "WRITE_SIZE run of --counters into the per-launch traffic summary "
-                         f"{TRAFFIC_FILE}, then exit")
+                         "WRITE_SIZE run of --counters into the per-launch traffic summaries "
+                         "of the kernels the run dispatched ("
+                         + ", ".join(d["traffic_file"] for d in DOMINANT.values()) + "), then exit")
     return ap.parse_args()
 
 
-def source_hash() -> str:
-    """sha256 over the sources the Metropolis pass kernel is compiled from."""
+def source_hash(name: str) -> str:
+    """sha256 over the sources a dominant-kernel candidate is compiled from."""
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in DOMINANT[name]["sources"]:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -119,50 +143,58 @@ def read_counter_csv(path):
 
 
 def reduce_counters(fetch_csv, write_csv):
-    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the Metropolis pass, each scaled
-    by what the same counter reads for the 1 GiB device copy of the --counters run."""
+    """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each dominant-kernel candidate the
+    run dispatched, each scaled by what the same counter reads for the 1 GiB device copy
+    of the --counters run."""
     fetch, write = read_counter_csv(fetch_csv), read_counter_csv(write_csv)
 
     def pick(d, key):
         names = [n for n in d if key(n)]
-        if len(names) != 1:
+        if len(names) > 1:
             raise SystemExit(f"expected one kernel, found {names}")
-        return d[names[0]]
-    def is_copy(n):
-        return "copy" in n.lower()
+        return d[names[0]] if names else None
 
-    def mh(n):  # colour_pass_kernel<float, (hsg::PassMode)0, false>: binary32 Metropolis
-        return "colour_pass_kernel<float" in n and "PassMode)0, false>" in n
-
-    copy_f, copy_w = pick(fetch, is_copy), pick(write, is_copy)
-    mh_f, mh_w = pick(fetch, mh), pick(write, mh)
+    copy_f = pick(fetch, lambda n: "copy" in n.lower())
+    copy_w = pick(write, lambda n: "copy" in n.lower())
+    if copy_f is None or copy_w is None:
+        raise SystemExit("no device copy in the counter runs")
     gib_kib = float(1 << 20)
     f_scale = gib_kib / max(copy_f)
     w_scale = gib_kib / max(copy_w)
-    f_b = sum(mh_f) / len(mh_f) * 1024 * f_scale
-    w_b = sum(mh_w) / len(mh_w) * 1024 * w_scale
-    lines = [
-        "# HBM traffic of one Metropolis colour pass, L=256 binary32, k=4 (counter runs)",
-        f"# commands: rocprofv3 --pmc FETCH_SIZE -d <dir> --output-format csv -- "
-        f"python bench.py --counters   (then the same with WRITE_SIZE)",
-        f"#           python bench.py --reduce-counters <fetch csv> <write csv>",
-        f"copy_fetch_kib={max(copy_f):.0f} fetch_scale={f_scale:.4f}",
-        f"copy_write_kib={max(copy_w):.0f} write_scale={w_scale:.4f}",
-        f"dispatches={len(mh_f)}",
-        f"fetch_bytes_per_launch={f_b:.0f}",
-        f"write_bytes_per_launch={w_b:.0f}",
-        f"algorithmic_bytes_per_launch={(1 << 23) * BYTES_PER_SITE_PHASE:.0f}",
-        f"source_hash={source_hash()}",
-    ]
-    with open(os.path.join(ROOT, TRAFFIC_FILE), "w") as f:
-        f.write("\n".join(lines) + "\n")
-    print("\n".join(lines))
+    written = 0
+    for name, d in DOMINANT.items():
+        k_f = pick(fetch, lambda n: d["trace_name"] in n)
+        k_w = pick(write, lambda n: d["trace_name"] in n)
+        if k_f is None or k_w is None:
+            continue
+        f_b = sum(k_f) / len(k_f) * 1024 * f_scale
+        w_b = sum(k_w) / len(k_w) * 1024 * w_scale
+        lines = [
+            f"# HBM traffic of {d['title']} ({d['kernel']}), L=256 binary32, k=4",
+            "# commands: rocprofv3 --pmc FETCH_SIZE -d <dir> -o run --output-format csv -- "
+            "python bench.py --counters   (then the same with WRITE_SIZE)",
+            "#           python bench.py --reduce-counters <fetch csv> <write csv>",
+            f"copy_fetch_kib={max(copy_f):.0f} fetch_scale={f_scale:.4f}",
+            f"copy_write_kib={max(copy_w):.0f} write_scale={w_scale:.4f}",
+            f"dispatches={len(k_f)}",
+            f"fetch_bytes_per_launch={f_b:.0f}",
+            f"write_bytes_per_launch={w_b:.0f}",
+            f"algorithmic_bytes_per_launch={(1 << 24) * d['sites'] * BYTES_PER_SITE_PHASE:.0f}",
+            f"source_hash={source_hash(name)}",
+        ]
+        with open(os.path.join(ROOT, d["traffic_file"]), "w") as f:
+            f.write("\n".join(lines) + "\n")
+        print("\n".join(lines))
+        written += 1
+    if not written:
+        raise SystemExit("none of the dominant-kernel candidates was dispatched")
 
 
-def measured_traffic():
-    """Copy-calibrated HBM bytes per Metropolis pass launch from the committed counter
-    summary, or None when the kernel sources changed since the counters were taken."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+def measured_traffic(name: str):
+    """Copy-calibrated HBM bytes per launch of a dominant-kernel candidate from its
+    committed counter summary, or None when its sources changed since the counters were
+    taken."""
+    path = os.path.join(ROOT, DOMINANT[name]["traffic_file"])
     if not os.path.exists(path):
         return None
     kv = {}
@@ -172,7 +204,7 @@ def measured_traffic():
                 for item in line.split():
                     k, _, v = item.partition("=")
                     kv[k] = v
-    if kv.get("source_hash") != source_hash():
+    if kv.get("source_hash") != source_hash(name):
         return None
     return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
@@ -193,7 +225,8 @@ def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup, flags=0):
 
 def binary64_leg(hsg, args, torch, flags):
     """The headline sweep with binary64 spins and couplings (the large-lattice
-    configuration compares binary32 with binary64): same L, k, n_or, T and traversal."""
+    configuration compares binary32 with binary64): same L, k, n_or and T, with the
+    library's traversal for binary64."""
     L = args.L
     lat = hsg.Lattice(L, torch.float64, seed=1)
     steps = max(5, args.steps // 5)
@@ -201,7 +234,7 @@ def binary64_leg(hsg, args, torch, flags):
                      steps=steps, warmup=2, flags=flags)
     del lat
     torch.cuda.empty_cache()
-    return {"dtype": "f64", "steps": steps, "ms_per_step": ms,
+    return {"dtype": "f64", "steps": steps, "ms_per_step": ms, "flags": flags,
             "spin_updates_per_ns": L ** 3 * (args.k + args.n_or) / (ms * 1e6)}
 
 
@@ -389,9 +422,11 @@ def main():
     if args.flags is not None:
         flags = args.flags
     elif args.counters:
-        flags = hsg.HSG_SNAKE  # pass by pass: both kinds of colour pass are counted
+        # both dominant-kernel candidates are dispatched: Metropolis colour passes and
+        # over-relaxation phases that carry the next colour-0 Metropolis pass
+        flags = hsg.HSG_SNAKE | hsg.HSG_PHASE_MC
     elif args.no_autotune:
-        flags = hsg.default_flags(L)
+        flags = hsg.default_flags(L, torch.float32)
     else:
         from paper_1006_2566_amd import autotune
         flags = autotune.sweep_flags(L, torch.float32, k=args.k, n_or=args.n_or, T=args.T,
@@ -418,11 +453,10 @@ def main():
                          "hbm_frac_36B": N * (1 + args.n_or) * BYTES_PER_SITE_PHASE /
                          (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
 
-    # dominant kernel: the Metropolis colour pass (half the sites, k hits each).  Its
-    # average duration: Metropolis-only sweeps (two passes each, one energy fold per
-    # call) timed with events on the launch stream.  The over-relaxation pass, bound
-    # by HBM, is timed the same way.
-    pass_flags = flags & ~(hsg.HSG_FUSED | hsg.HSG_PHASE_LAUNCH)  # one launch per colour pass
+    # The Metropolis colour pass (half the sites, k hits each): its average duration from
+    # Metropolis-only sweeps (two passes each, one energy fold per call) timed with events
+    # on the launch stream.  The over-relaxation pass, bound by HBM, is timed the same way.
+    pass_flags = flags & ~(hsg.HSG_FUSED | hsg.HSG_PHASE_LAUNCH | hsg.HSG_PHASE_MC)
     ms_mh_pass = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=args.steps,
                              warmup=2, flags=pass_flags) / 2.0
     ms_or_pass = time_sweeps(lat, torch, T=args.T, k=0, n_or=1, R=0, steps=args.steps,
@@ -430,30 +464,61 @@ def main():
     # the over-relaxation phase as one launch (when the traversal uses it): both passes
     # of the phase, 36 B per site algorithmic
     or_phase = None
-    if flags & hsg.HSG_PHASE_LAUNCH and hsg.phase_supported(L):
+    phase = bool(flags & (hsg.HSG_PHASE_LAUNCH | hsg.HSG_PHASE_MC)) and hsg.phase_supported(L)
+    if phase:
         ms_ph = time_sweeps(lat, torch, T=args.T, k=0, n_or=1, R=0, steps=args.steps, warmup=2,
                             flags=flags)
         gbs = N * BYTES_PER_SITE_PHASE / (ms_ph * 1e-3) / 1e9
-        or_phase = {"kernel": "phase_kernel<float, OverRelax>", "bound": "hbm",
+        or_phase = {"kernel": "phase_kernel<float, 2, OverRelax>", "bound": "hbm",
                     "kernel_ms": ms_ph, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
     head = per_k[str(args.k)]
     sites_pass = N / 2
     ops_pass = sites_pass * ops_per_site_pass(args.k)
     achieved = ops_pass / (ms_mh_pass * 1e-3) / 1e12
-    traffic = measured_traffic() if (L == 256 and args.k == 4) else None
-    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                "frac": achieved / ALU_PEAK_TOPS, "traffic": traffic,
-                "kernel": "colour_pass_kernel<float, Metropolis>", "kernel_ms": ms_mh_pass,
-                "ops_per_launch": ops_pass,
-                "hits_per_ns": sites_pass * args.k / (ms_mh_pass * 1e6),
-                "hbm_frac_36B": sites_pass * BYTES_PER_SITE_PHASE / (ms_mh_pass * 1e-3) / 1e9 /
-                HBM_PEAK_GBS,
-                "overrelax_pass": {"bound": "hbm", "kernel_ms": ms_or_pass,
-                                   "achieved_GBs": sites_pass * BYTES_PER_SITE_PHASE /
-                                   (ms_or_pass * 1e-3) / 1e9,
-                                   "frac": sites_pass * BYTES_PER_SITE_PHASE /
-                                   (ms_or_pass * 1e-3) / 1e9 / HBM_PEAK_GBS},
-                "overrelax_phase": or_phase}
+    counted = L == 256 and args.k == 4
+    metropolis = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                  "frac": achieved / ALU_PEAK_TOPS,
+                  "traffic": measured_traffic("metropolis_pass") if counted else None,
+                  "kernel": DOMINANT["metropolis_pass"]["kernel"], "kernel_ms": ms_mh_pass,
+                  "ops_per_launch": ops_pass,
+                  "hits_per_ns": sites_pass * args.k / (ms_mh_pass * 1e6),
+                  "hbm_frac_36B": sites_pass * BYTES_PER_SITE_PHASE / (ms_mh_pass * 1e-3) /
+                  1e9 / HBM_PEAK_GBS}
+    extras = {"overrelax_pass": {"bound": "hbm", "kernel_ms": ms_or_pass,
+                                 "achieved_GBs": sites_pass * BYTES_PER_SITE_PHASE /
+                                 (ms_or_pass * 1e-3) / 1e9,
+                                 "frac": sites_pass * BYTES_PER_SITE_PHASE /
+                                 (ms_or_pass * 1e-3) / 1e9 / HBM_PEAK_GBS},
+              "overrelax_phase": or_phase}
+    if phase and flags & hsg.HSG_PHASE_MC and args.k > 0 and args.n_or > 0:
+        # Dominant kernel: the over-relaxation phase with the next sweep's colour-0
+        # Metropolis pass.  A call of n sweeps runs n + 1 Metropolis passes, n - 1 such
+        # launches, (n - 1)(n_or - 1) + n_or plain phases and fixed per-call work, so the
+        # growth of the call's time per sweep (two call lengths, events on the launch
+        # stream) less a Metropolis pass and n_or - 1 phases is the launch's duration.
+        n1, n2 = max(4, args.steps // 5), max(args.steps, 2 * max(4, args.steps // 5))
+        tot = [time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=0, steps=n,
+                           warmup=2, flags=flags) * n for n in (n1, n2)]
+        ms_f = (tot[1] - tot[0]) / (n2 - n1) - ms_mh_pass - (args.n_or - 1) * or_phase["kernel_ms"]
+        bytes_f = N * BYTES_PER_SITE_PHASE
+        ops_f = sites_pass * ops_per_site_pass(args.k) + N * OPS_PER_SITE_OR
+        gbs_f = bytes_f / (ms_f * 1e-3) / 1e9
+        tops_f = ops_f / (ms_f * 1e-3) / 1e12
+        # the larger of the two floors binds: the phase's compulsory bytes at HBM peak
+        # against both passes' lane operations at the vector peak
+        hbm_bound = bytes_f / HBM_PEAK_GBS >= ops_f / (ALU_PEAK_TOPS * 1e3)
+        roofline = {"bound": "hbm" if hbm_bound else "alu",
+                    "achieved": gbs_f if hbm_bound else tops_f,
+                    "peak": HBM_PEAK_GBS if hbm_bound else ALU_PEAK_TOPS,
+                    "unit": "GB/s" if hbm_bound else "TOP/s",
+                    "frac": gbs_f / HBM_PEAK_GBS if hbm_bound else tops_f / ALU_PEAK_TOPS,
+                    "traffic": measured_traffic("phase_mc") if counted else None,
+                    "kernel": DOMINANT["phase_mc"]["kernel"], "kernel_ms": ms_f,
+                    "bytes_per_launch": bytes_f, "ops_per_launch": ops_f,
+                    "alu_achieved": tops_f, "alu_frac": tops_f / ALU_PEAK_TOPS,
+                    "metropolis_pass": metropolis, **extras}
+    else:
+        roofline = {**metropolis, **extras}
 
     rec = {"metric": METRIC,
            "value": head["spin_updates_per_ns"], "unit": "spin updates/ns", "n_gpus": 1,
@@ -466,7 +531,8 @@ def main():
                       "L": L, "k": args.k, "n_or": args.n_or, "T": args.T, "flags": flags},
            "per_k": per_k, "roofline": roofline}
     if not args.no_binary64:
-        rec["binary64"] = binary64_leg(hsg, args, torch, flags)
+        rec["binary64"] = binary64_leg(hsg, args, torch, flags if args.flags is not None
+                                       else hsg.default_flags(L, torch.float64))
     if not args.no_observables:
         rec["observables"] = observables_leg(hsg, lat, torch, args.steps)
     if args.batch_cycles > 0:

@@ -86,6 +86,13 @@ extern "C" {
                                window of planes in LDS, reading and writing the spins once
                                (L a multiple of 64, L >= 64; else ignored).  Uses the second
                                spin array of the work buffer.  Not with HSG_FUSED */
+#define HSG_PHASE_MC 256   /* as HSG_PHASE_LAUNCH, and when a sweep of the call is followed
+                               by another (k_hits > 0), the launch of its last
+                               over-relaxation phase also runs the next sweep's colour-0
+                               Monte Carlo pass on each workgroup's own sites, after the
+                               phase (renormalisation between them when due).  The Monte
+                               Carlo arithmetic, which is never recomputed, hides the
+                               phase's memory traffic.  Not with HSG_FUSED */
 #define HSG_STREAM_LOADS 64 /* couplings and the other colour's spins, which a pass only
                                reads, are loaded with the non-temporal cache hint: the
                                nearest this GPU has to the texture path of the TEXT variant.
@@ -110,7 +117,8 @@ typedef struct hsg_sweep_params {
   int32_t renorm_every; /* R > 0: after sweep s with (s+1) % R == 0 every spin is
                            divided by its length; 0 = never */
   int32_t flags;        /* OR of HSG_HEAT_BATH, HSG_SNAKE, HSG_FUSED, HSG_MARCH_PHASE,
-                           HSG_PLANE_LAUNCH, HSG_STREAM_LOADS */
+                           HSG_PLANE_LAUNCH, HSG_STREAM_LOADS, HSG_PHASE_LAUNCH,
+                           HSG_PHASE_MC */
 } hsg_sweep_params;
 
 /* Sizes of the three device buffers of an L^3 lattice of the given dtype.  Any

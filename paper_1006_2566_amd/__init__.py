@@ -31,6 +31,7 @@ HSG_MARCH_PHASE = 16
 HSG_PLANE_LAUNCH = 32
 HSG_STREAM_LOADS = 64
 HSG_PHASE_LAUNCH = 128
+HSG_PHASE_MC = 256
 FUSED_MIN_L, FUSED_MAX_L = 256, 1024
 FOURIER_VALUES = 65
 L_MAX = 1290
@@ -46,12 +47,16 @@ def phase_supported(L: int) -> bool:
     return L >= 64 and L % 64 == 0
 
 
-def default_flags(L: int) -> int:
+def default_flags(L: int, dtype=None) -> int:
     """Traversal flags of a sweep that names none: Monte Carlo passes one launch each in
     alternating z order, over-relaxation phases as one launch each where the lattice
-    gives that launch enough workgroups (L >= 256), which measures fastest on MI355X
+    gives that launch enough workgroups (L >= 256) -- in binary32 with the next sweep's
+    colour-0 Monte Carlo pass in the same launch -- which measures fastest on MI355X
     (HSG_FUSED is opt-in).  Spins are the same either way."""
-    return HSG_SNAKE | (HSG_PHASE_LAUNCH if L >= 256 and phase_supported(L) else 0)
+    if not (L >= 256 and phase_supported(L)):
+        return HSG_SNAKE
+    f64 = dtype is not None and str(dtype) in ("torch.float64", "float64")
+    return HSG_SNAKE | (HSG_PHASE_LAUNCH if f64 else HSG_PHASE_MC)
 
 
 class HsgError(RuntimeError):
@@ -197,8 +202,8 @@ class Lattice:
     def sweep(self, T: float, k: int = 1, n_or: int = 0, renorm_every: int = 0,
               n_sweeps: int = 1, heat_bath: bool = False, flags: int | None = None,
               stream=None) -> None:
-        """n_sweeps sweeps; flags None = default_flags(L)."""
-        f = default_flags(self.L) if flags is None else int(flags)
+        """n_sweeps sweeps; flags None = default_flags(L, dtype)."""
+        f = default_flags(self.L, self.dtype) if flags is None else int(flags)
         p = _SweepParams(float(T), int(k), int(n_or), int(renorm_every),
                          (HSG_HEAT_BATH if heat_bath else 0) | f)
         check(lib().hsg_sweep(ctypes.byref(self._d), ctypes.byref(p), int(n_sweeps),

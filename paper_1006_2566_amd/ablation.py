@@ -17,6 +17,8 @@ sweep flags, and every analogue computes exactly the default schedule's spins:
     PH    HSG_SNAKE | HSG_PHASE_LAUNCH       each over-relaxation phase as one launch (a
                                              lean one-phase LDS march; Metropolis phases
                                              pass by pass as in GM+S)
+    PH+MC HSG_SNAKE | HSG_PHASE_MC           PH, the launch of each phase also running the
+                                             next sweep's colour-0 Metropolis pass
 
 The march needs 256 <= L <= 1024 (L a multiple of 64); elsewhere SM and SM4P are
 reported as unsupported.  Workloads: over-relaxation only (the paper's Table 2) and
@@ -33,8 +35,8 @@ import json
 
 import torch
 
-from . import (HSG_FUSED, HSG_MARCH_PHASE, HSG_PHASE_LAUNCH, HSG_PLANE_LAUNCH, HSG_SNAKE,
-               HSG_STREAM_LOADS, Lattice, fused_supported)
+from . import (HSG_FUSED, HSG_MARCH_PHASE, HSG_PHASE_LAUNCH, HSG_PHASE_MC, HSG_PLANE_LAUNCH,
+               HSG_SNAKE, HSG_STREAM_LOADS, Lattice, fused_supported)
 
 VARIANTS = {
     "GM": 0,
@@ -44,6 +46,7 @@ VARIANTS = {
     "SM": HSG_FUSED | HSG_MARCH_PHASE,
     "SM4P": HSG_FUSED,
     "PH": HSG_SNAKE | HSG_PHASE_LAUNCH,
+    "PH+MC": HSG_SNAKE | HSG_PHASE_MC,
 }
 
 

@@ -19,7 +19,8 @@ from typing import Callable, Iterable
 
 import torch
 
-from . import HSG_FUSED, HSG_PHASE_LAUNCH, HSG_SNAKE, Lattice, fused_supported, phase_supported
+from . import (HSG_FUSED, HSG_PHASE_LAUNCH, HSG_PHASE_MC, HSG_SNAKE, Lattice, fused_supported,
+               phase_supported)
 
 CACHE_ENV = "HSG_AUTOTUNE_CACHE"
 
@@ -91,11 +92,14 @@ def sweep_flags(L: int, dtype: torch.dtype = torch.float32, k: int = 4, n_or: in
                 heat_bath: bool = False, T: float = 0.3, renorm_every: int = 10,
                 retune: bool = False, path: str | None = None) -> int:
     """Traversal flags for hsg_sweep on an L^3 lattice: plain order, alternating z
-    order (HSG_SNAKE), over-relaxation phases in one launch each (HSG_PHASE_LAUNCH) or
+    order (HSG_SNAKE), over-relaxation phases in one launch each (HSG_PHASE_LAUNCH), the
+    same with the next sweep's colour-0 Monte Carlo pass in that launch (HSG_PHASE_MC) or
     fused passes (HSG_FUSED), where the lattice allows them."""
     cands = [0, HSG_SNAKE]
     if n_or > 0 and phase_supported(L):
         cands.append(HSG_SNAKE | HSG_PHASE_LAUNCH)
+        if k > 0:
+            cands.append(HSG_SNAKE | HSG_PHASE_MC)
     if fused_supported(L):
         cands.append(HSG_FUSED)
     key = f"sweep L={L} {str(dtype).replace('torch.', '')} k={k} n_or={n_or} hb={int(heat_bath)}"
@@ -103,7 +107,7 @@ def sweep_flags(L: int, dtype: torch.dtype = torch.float32, k: int = 4, n_or: in
     def measure(flags):
         lat = Lattice(L, dtype, seed=1)
         return _event_ms(lambda: lat.sweep(T=T, k=k, n_or=n_or, renorm_every=renorm_every,
-                                           n_sweeps=2, heat_bath=heat_bath, flags=flags), 3)
+                                           n_sweeps=4, heat_bath=heat_bath, flags=flags), 3)
     return int(pick(key, cands, measure, retune=retune, path=path))
 
 

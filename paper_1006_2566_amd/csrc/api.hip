@@ -60,13 +60,14 @@ int check_params(const hsg_sweep_params* p) {
     return fail(HSG_EINVAL, "k_hits must be < 65536 and n_or < 32768");
   if (p->renorm_every < 0) return fail(HSG_EINVAL, "renorm_every must be >= 0");
   if (p->flags & ~(HSG_HEAT_BATH | HSG_SNAKE | HSG_FUSED | HSG_MARCH_PHASE | HSG_PLANE_LAUNCH |
-                   HSG_STREAM_LOADS | HSG_PHASE_LAUNCH))
+                   HSG_STREAM_LOADS | HSG_PHASE_LAUNCH | HSG_PHASE_MC))
     return fail(HSG_EINVAL, "unknown flags 0x%x", (unsigned)p->flags);
   if ((p->flags & HSG_MARCH_PHASE) && !(p->flags & HSG_FUSED))
     return fail(HSG_EINVAL, "HSG_MARCH_PHASE needs HSG_FUSED");
-  if ((p->flags & HSG_FUSED) && (p->flags & (HSG_PLANE_LAUNCH | HSG_STREAM_LOADS | HSG_PHASE_LAUNCH)))
-    return fail(HSG_EINVAL, "HSG_PLANE_LAUNCH, HSG_STREAM_LOADS and HSG_PHASE_LAUNCH apply to the "
-                            "pass-by-pass schedule, not to HSG_FUSED");
+  if ((p->flags & HSG_FUSED) &&
+      (p->flags & (HSG_PLANE_LAUNCH | HSG_STREAM_LOADS | HSG_PHASE_LAUNCH | HSG_PHASE_MC)))
+    return fail(HSG_EINVAL, "HSG_PLANE_LAUNCH, HSG_STREAM_LOADS, HSG_PHASE_LAUNCH and HSG_PHASE_MC "
+                            "apply to the pass-by-pass schedule, not to HSG_FUSED");
   return HSG_OK;
 }
 
@@ -84,7 +85,10 @@ bool renorm_due(const hsg_sweep_params* p, uint64_t sweep) {
 // HSG_PLANE_LAUNCH one launch per z slab of tiles (one z plane from L = 64 up).  With
 // HSG_PHASE_LAUNCH each over-relaxation phase is one launch reading one spin array and
 // writing the other (the lattice's and the work buffer's second one); after an odd
-// number of them the spins are copied back at the end of the call.
+// number of them the spins are copied back at the end of the call.  With HSG_PHASE_MC
+// the launch of a sweep's last over-relaxation phase also runs the colour-0 Monte Carlo
+// pass of the next sweep of the call (and the renormalisation between them when due);
+// that sweep then starts with its colour-1 pass.
 template <typename R>
 int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
   using namespace hsg;
@@ -93,7 +97,9 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   PassArgs<R> a{};
   R* bufs[2] = {(R*)lat->spins, (R*)((char*)lat->work + fused_offset(lat->L))};
   int cur = 0;  // buffer holding the current spins (phase launches flip it)
-  const bool phase_launch = (p->flags & HSG_PHASE_LAUNCH) && phase_supported(lat->L);
+  const bool phase_launch =
+      (p->flags & (HSG_PHASE_LAUNCH | HSG_PHASE_MC)) && phase_supported(lat->L);
+  const bool phase_mc = phase_launch && (p->flags & HSG_PHASE_MC) && p->k_hits > 0;
   PhaseArgs<R> ph{};
   ph.J = (const R*)lat->J;
   ph.beta = (R)(1.0 / p->T);
@@ -111,32 +117,46 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   a.g = g;
   a.nt = (p->flags & HSG_STREAM_LOADS) ? 1 : 0;
   const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
+  ph.mc_mode = (int32_t)mc;
+  ph.partials = pass_partials(lat->work);
   const bool snake = (p->flags & HSG_SNAKE) != 0;
   const bool by_slab = (p->flags & HSG_PLANE_LAUNCH) != 0;
   const int32_t slab_tiles = g.tiles_x * g.tiles_y;
   int32_t pass_count = 0;
+  bool mc0_done = false;  // this sweep's colour-0 Monte Carlo pass ran in the last launch
   for (int32_t n = 0; n < n_sweeps; ++n) {
     const uint64_t sweep = lat->sweep + (uint64_t)n;
     a.sweep = (uint32_t)sweep;
+    bool renorm_done = false;
     for (int32_t phase = 0; phase <= p->n_or; ++phase) {
       if (phase == 0 && p->k_hits == 0) continue;
       a.phase = (uint32_t)phase;
       if (phase_launch && phase > 0) {
+        const bool then_mc = phase_mc && phase == p->n_or && n + 1 < n_sweeps;
         ph.in = bufs[cur];
         ph.out = bufs[1 - cur];
         ph.sweep = (uint32_t)sweep;
         ph.phase = (uint32_t)phase;
+        ph.then_mc = then_mc ? 1 : 0;
+        ph.mc_sweep = (uint32_t)(sweep + 1);
+        ph.renorm = then_mc && renorm_due(p, sweep) ? 1 : 0;
         int rc = device_status(launch_phase<R>(ph, st), "phase launch");
         if (rc) return rc;
         cur = 1 - cur;
         a.spins = planes_of<R>(bufs[cur], Nh);
         pass_count += 2;
+        mc0_done = then_mc;
+        renorm_done = ph.renorm != 0;
         continue;
       }
       for (int32_t colour = 0; colour < 2; ++colour) {
         a.colour = colour;
         a.reverse = snake ? (pass_count & 1) : 0;
         ++pass_count;
+        if (phase == 0 && colour == 0 && mc0_done) {
+          mc0_done = false;
+          continue;
+        }
         const PassMode mode = phase == 0 ? mc : PassMode::OverRelax;
         if (!by_slab) {
           a.tile_base = 0;
@@ -154,7 +174,7 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
         }
       }
     }
-    if (renorm_due(p, sweep)) {
+    if (renorm_due(p, sweep) && !renorm_done) {
       int rc = device_status(launch_renormalise<R>(lat->L, bufs[cur], 2, st), "renormalise");
       if (rc) return rc;
     }
@@ -338,9 +358,10 @@ int hsg_sweep(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, voi
   if (use_fused(lat, p) && lat->work_bytes < hsg::work_bytes_for(lat->L, (int32_t)elem))
     return fail(HSG_EINVAL, "HSG_FUSED needs a work buffer of %zu bytes (has %zu)",
                 hsg::work_bytes_for(lat->L, (int32_t)elem), lat->work_bytes);
-  if ((p->flags & HSG_PHASE_LAUNCH) && hsg::phase_supported(lat->L) && p->n_or > 0 &&
-      lat->work_bytes < hsg::work_bytes_for(lat->L, (int32_t)elem))
-    return fail(HSG_EINVAL, "HSG_PHASE_LAUNCH needs a work buffer of %zu bytes (has %zu)",
+  if ((p->flags & (HSG_PHASE_LAUNCH | HSG_PHASE_MC)) && hsg::phase_supported(lat->L) &&
+      p->n_or > 0 && lat->work_bytes < hsg::work_bytes_for(lat->L, (int32_t)elem))
+    return fail(HSG_EINVAL, "HSG_PHASE_LAUNCH and HSG_PHASE_MC need a work buffer of %zu bytes "
+                            "(has %zu)",
                 hsg::work_bytes_for(lat->L, (int32_t)elem), lat->work_bytes);
   hipStream_t st = as_stream(stream);
   rc = lat->dtype == HSG_F32 ? sweep_impl<float>(lat, p, n_sweeps, st)

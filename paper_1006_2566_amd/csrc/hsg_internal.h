@@ -110,9 +110,9 @@ struct MarchArgs {
   MarchStage st[kMarchMaxStages];
 };
 
-// An over-relaxation phase (colour-0 pass then colour-1 pass) in one launch
-// (kernels_phase.hip).  Tile shape timed on MI355X at L = 256 against 128-1024
-// threads, 4-32 rows and 16-64 planes.
+// An over-relaxation phase (colour-0 pass then colour-1 pass) in one launch, optionally
+// followed by the next sweep's colour-0 Monte Carlo pass (kernels_phase.hip).  Tile
+// shape timed on MI355X at L = 256 against 128-1024 threads, 4-32 rows and 16-64 planes.
 constexpr int kPhaseThreads = 512;
 constexpr int kPTY = 16;  // tile rows
 constexpr int kPZ = 32;   // planes per workgroup
@@ -123,11 +123,21 @@ struct PhaseArgs {
   const R* in;  // colour-split spins before the phase
   R* out;       // after it (distinct from in)
   const R* J;   // colour-split couplings
-  R beta;       // (the Philox context of the site update; over-relaxation draws none)
+  R beta;       // inverse temperature of the Monte Carlo pass
   uint32_t seed_lo, seed_hi;
-  uint32_t sweep, phase;
+  uint32_t sweep, phase;  // Philox counter words of the phase (over-relaxation draws none)
   int32_t k_hits;
   int32_t L;
+  // With then_mc: after the phase, the colour-0 pass of the Monte Carlo phase of sweep
+  // mc_sweep (mode mc_mode, a PassMode other than OverRelax).  With renorm, every spin
+  // is divided by its length between the two (colour 1 right after its over-relaxation
+  // step, colour 0 right before its Monte Carlo update).  The energy changes of a
+  // workgroup's sites are added to partials[blockIdx.x].
+  int32_t then_mc;
+  int32_t mc_mode;
+  uint32_t mc_sweep;
+  int32_t renorm;
+  double* partials;
 };
 
 bool phase_supported(int32_t L);

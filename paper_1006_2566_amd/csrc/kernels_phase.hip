@@ -1,21 +1,35 @@
 // One over-relaxation phase of the checkerboard schedule (§4) -- the colour-0 pass and
-// then the colour-1 pass -- in one launch, reading the spins once and writing them once.
+// then the colour-1 pass -- in one launch, reading the spins once and writing them once;
+// optionally followed, in the same launch, by the colour-0 pass of the next sweep's
+// Monte Carlo phase.
 //
-// Each workgroup owns a tile of 64 x kPTY sites in (x, y) and kPZ planes in z, and
-// marches through z holding, in LDS, three planes of each colour of its region (the
-// tile widened by one colour site on each side in x and by two rows in y): colour 1 on
-// planes a - 1 .. a + 1, colour 0 on planes a - 2 .. a.  At step t it
-// updates the colour-0 sites of plane a = z0 - 1 + t over the tile and a ring of one
-// site (stage A), then the colour-1 sites of plane a - 1 over the tile (stage B), whose
-// colour-0 neighbours on planes a - 2, a - 1 and a are then all updated.  The ring
-// and the planes z0 - 1 and z0 + kPZ belong to other workgroups, which compute them
-// too, from the same inputs and the same Philox draws, hence to the same bits; so
-// workgroups never communicate.  They read the spins before the phase from one
-// buffer and write the tile after it to another.
+// Each workgroup owns a tile of 64 x kPTY sites in (x, y) and a run of planes in z, and
+// marches through z holding, in LDS, a few planes of each colour of its region.  With NS
+// stages (2: the phase; 3: the phase and the Monte Carlo pass) stage s updates its
+// colour on the tile and a ring of NS - 1 - s sites around it, so that the next stage
+// finds every neighbour it reads already updated; the region is the tile widened by NS
+// sites on each side (NS - 1 colour columns in x, NS rows in y).  With a = z0 - (NS - 1)
+// + t the plane of stage A at step t:
 //
-// The site arithmetic (field of eq. 2 in the fixed order of the single-pass kernel,
-// then the reflection of §4) is the single pass's, so results equal two colour passes
-// bit for bit.
+//   stage A   colour 0, over-relaxation, ring NS - 1, plane a
+//   stage B   colour 1, over-relaxation, ring NS - 2, plane a - 1 (reads colour 0 on
+//             a - 2 .. a)
+//   stage C   colour 0, Monte Carlo, the tile only, plane a - 2 (reads colour 1 on
+//             a - 3 .. a - 1)
+//
+// The ring and the planes outside the tile's own belong to other workgroups, which
+// compute them too, from the same inputs and the same Philox draws, hence to the same
+// bits; so workgroups never communicate.  They read the spins before the launch from one
+// buffer and write the tile after it to another.  Stage C runs on the tile only: the
+// expensive Monte Carlo update is never recomputed, and the phase's spin traffic (the
+// planes in LDS) serves the Monte Carlo pass too.
+//
+// The site arithmetic (field of eq. 2 in the fixed order of the single-pass kernel, then
+// the reflection of §4 or the k Metropolis hits / heat-bath draws) is the single pass's,
+// so results equal the pass-by-pass schedule bit for bit; only the order in which the
+// binary64 energy changes of stage C are summed differs.
+#include <type_traits>
+
 #include "hsg_device.h"
 #include "hsg_internal.h"
 #include "hsg_site.h"
@@ -23,19 +37,42 @@
 namespace hsg {
 namespace {
 
-constexpr int kPTX = 32;                 // colour sites of a tile row (64 sites in x)
-constexpr int kRegX = kPTX + 2;          // region row: xh0 - 1 .. xh0 + 32
-constexpr int kRegY = kPTY + 4;          // region rows: y0 - 2 .. y0 + kPTY + 1
-constexpr int kColour = kRegY * kRegX;   // one colour, one component, one plane
-constexpr int kSlice = 3 * kColour;      // one colour, three components, one plane
-constexpr int kRing = 3;                 // planes of each colour in LDS
-constexpr int kLoadRounds = (kSlice + kPhaseThreads - 1) / kPhaseThreads;
-constexpr int kASites = (kPTY + 2) * (kPTX + 1);  // colour-0 sites of stage A per plane
-constexpr int kARounds = (kASites + kPhaseThreads - 1) / kPhaseThreads;
-constexpr int kBSites = kPTY * kPTX;                // colour-1 sites of stage B per plane
-constexpr int kBRounds = (kBSites + kPhaseThreads - 1) / kPhaseThreads;
-constexpr int kStore = 2 * 3 * kPTY * kPTX;         // values of a plane's own tile
-constexpr int kStoreRounds = (kStore + kPhaseThreads - 1) / kPhaseThreads;
+constexpr int kPTX = 32;      // colour sites of a tile row (64 sites in x)
+constexpr int kHitGroup = 4;  // Monte Carlo hits whose draws are computed together
+
+__device__ __forceinline__ int32_t wrap_to(int32_t v, int32_t n) {
+  return v < 0 ? v + n : (v >= n ? v - n : v);
+}
+
+// The LDS window of a march with NS stages and THREADS threads.  Region column j holds
+// colour column xh0 - OX + j, region row ry holds row y0 - OY + ry.  Colour 0 keeps K0
+// planes, colour 1 K1 planes (stage C reads colour 1 on planes behind stage A's).
+template <int NS, int K0_, int K1_, int THREADS_>
+struct Win {
+  static constexpr int OX = NS - 1;
+  static constexpr int OY = NS;
+  static constexpr int RX = kPTX + 2 * OX;
+  static constexpr int RY = kPTY + 2 * OY;
+  static constexpr int COLOUR = RY * RX;  // one colour, one component, one plane
+  static constexpr int SLICE = 3 * COLOUR;  // one colour, three components, one plane
+  static constexpr int K0 = K0_;
+  static constexpr int K1 = K1_;
+  static constexpr int THREADS = THREADS_;
+  static constexpr int LOAD_ROUNDS = (SLICE + THREADS - 1) / THREADS;
+};
+using WinPhase = Win<2, 3, 3, kPhaseThreads>;  // the phase
+using WinMc = Win<3, 3, 5, kPhaseThreads>;     // the phase and stage C
+
+// The sites a stage with ring H updates on one plane: rows OY - H .. OY + kPTY + H - 1,
+// kPTX + H sites of the stage's colour in each.  On a row whose sites of that colour
+// have x parity p, the first sits in region column OX - (H + p) / 2.
+template <class W, int H>
+struct StageShape {
+  static constexpr int PER_ROW = kPTX + H;
+  static constexpr int ROWS = kPTY + 2 * H;
+  static constexpr int COUNT = PER_ROW * ROWS;
+  static constexpr int RY0 = W::OY - H;
+};
 
 struct PhaseCtx {
   int32_t L, Lh;
@@ -43,213 +80,348 @@ struct PhaseCtx {
   int32_t xh0, y0, z0;   // tile origin (colour column, row, plane)
 };
 
-__device__ __forceinline__ int32_t wrap_to(int32_t v, int32_t n) {
-  return v < 0 ? v + n : (v >= n ? v - n : v);
-}
-
 // One colour of a region plane in registers: element e (component, row, column) of
 // the slice, its colour-0 global offset without the plane's z offset (colour 1 adds
 // 3 N/2).
+template <class W>
 struct SliceOffsets {
-  uint32_t off[kLoadRounds];
+  uint32_t off[W::LOAD_ROUNDS];
 };
 
-template <typename R>
+template <typename R, class W>
 struct SliceRegs {
-  R v[kLoadRounds];
+  R v[W::LOAD_ROUNDS];
 };
 
-__device__ __forceinline__ void slice_offsets(SliceOffsets& so, const PhaseCtx& m) {
+template <class W>
+__device__ __forceinline__ void slice_offsets(SliceOffsets<W>& so, const PhaseCtx& m) {
 #pragma unroll
-  for (int k = 0; k < kLoadRounds; ++k) {
-    const int32_t e = (int32_t)threadIdx.x + k * kPhaseThreads;
-    const int32_t comp = e / kColour;
-    const int32_t r = e - comp * kColour;
-    const int32_t ry = r / kRegX;
-    const int32_t j = r - ry * kRegX;
-    const int32_t y = wrap_to(m.y0 - 2 + ry, m.L);
-    const int32_t xh = wrap_to(m.xh0 - 1 + j, m.Lh);
+  for (int k = 0; k < W::LOAD_ROUNDS; ++k) {
+    const int32_t e = (int32_t)threadIdx.x + k * W::THREADS;
+    const int32_t comp = e / W::COLOUR;
+    const int32_t r = e - comp * W::COLOUR;
+    const int32_t ry = r / W::RX;
+    const int32_t j = r - ry * W::RX;
+    const int32_t y = wrap_to(m.y0 - W::OY + ry, m.L);
+    const int32_t xh = wrap_to(m.xh0 - W::OX + j, m.Lh);
     so.off[k] = (uint32_t)comp * m.Nh + (uint32_t)xh + (uint32_t)m.Lh * (uint32_t)y;
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void fetch(SliceRegs<R>& sr, const SliceOffsets& so, const R* in,
-                                      const PhaseCtx& m, int32_t c, int32_t q) {
+template <typename R, class W>
+__device__ __forceinline__ void fetch(SliceRegs<R, W>& sr, const SliceOffsets<W>& so,
+                                      const R* in, const PhaseCtx& m, int32_t c, int32_t q) {
   const uint32_t base = (uint32_t)(3 * c) * m.Nh + m.zstride * (uint32_t)wrap_to(q, m.L);
 #pragma unroll
-  for (int k = 0; k < kLoadRounds; ++k)
-    if ((int32_t)threadIdx.x + k * kPhaseThreads < kSlice) sr.v[k] = in[so.off[k] + base];
+  for (int k = 0; k < W::LOAD_ROUNDS; ++k)
+    if ((int32_t)threadIdx.x + k * W::THREADS < W::SLICE) sr.v[k] = in[so.off[k] + base];
 }
 
-// Slice of colour c, plane q (q >= -3) in the colour's ring.
-template <typename R>
+// Slice of colour c, plane q (q >= -8) in the colour's ring.
+template <typename R, class W>
 __device__ __forceinline__ R* slice(R* lds, int32_t c, int32_t q) {
-  return lds + (c * kRing + (q + 3 * kRing) % kRing) * kSlice;
+  const int32_t slot = c == 0 ? (q + 8 * W::K0) % W::K0 : W::K0 + (q + 8 * W::K1) % W::K1;
+  return lds + slot * W::SLICE;
 }
 
-template <typename R>
-__device__ __forceinline__ void put(R* lds, const SliceRegs<R>& sr, int32_t c, int32_t q) {
-  R* dst = slice(lds, c, q);
+template <typename R, class W>
+__device__ __forceinline__ void put(R* lds, const SliceRegs<R, W>& sr, int32_t c, int32_t q) {
+  R* dst = slice<R, W>(lds, c, q);
 #pragma unroll
-  for (int k = 0; k < kLoadRounds; ++k) {
-    const int32_t e = (int32_t)threadIdx.x + k * kPhaseThreads;
-    if (e < kSlice) dst[e] = sr.v[k];
+  for (int k = 0; k < W::LOAD_ROUNDS; ++k) {
+    const int32_t e = (int32_t)threadIdx.x + k * W::THREADS;
+    if (e < W::SLICE) dst[e] = sr.v[k];
   }
 }
 
-// Update of the site of colour C in region row ry, column j, on plane q (z): the
-// field from the window (neighbour colour 1 - C), the six couplings from global memory
-// in the single pass's order, then apply_update; the result goes back to the window.
-template <typename R, int C, PassMode MODE>
-__device__ __forceinline__ double phase_site(R* lds, const R* J, const PhaseCtx& m,
-                                             int32_t q, int32_t z, int32_t ry, int32_t j,
-                                             const HitCtx<R>& hc) {
-  const R* cur = slice(lds, 1 - C, q);
-  const R* up = slice(lds, 1 - C, q + 1);
-  const R* dn = slice(lds, 1 - C, q - 1);
-  const int32_t y = wrap_to(m.y0 - 2 + ry, m.L);
-  const int32_t p = (y + z + C) & 1;  // x parity of colour-C sites on this row
-  const int32_t xh = wrap_to(m.xh0 - 1 + j, m.Lh);
-  const int32_t row = ry * kRegX;
-  const int32_t i_px = row + (p ? j + 1 : j), i_mx = row + (p ? j : j - 1);
-  const int32_t i_py = row + kRegX + j, i_my = row - kRegX + j, i_z = row + j;
-  // couplings: +x,+y,+z at the site (colour C planes), -x,-y,-z at the neighbours
-  const int32_t ym = y == 0 ? m.L - 1 : y - 1, zm = z == 0 ? m.L - 1 : z - 1;
-  const int32_t xhm = p ? xh : (xh == 0 ? m.Lh - 1 : xh - 1);
-  const uint32_t zo = m.zstride * (uint32_t)z;
-  const uint32_t own = zo + (uint32_t)m.Lh * (uint32_t)y + (uint32_t)xh;
+// Where site i of a stage with ring H (colour C) sits on plane q: region row and
+// column, periodic z, y, colour column and the x parity of the row's colour-C sites.
+struct SiteRef {
+  int32_t z, ry, j, y, xh, p;
+};
+
+template <class W, int C, int H>
+__device__ __forceinline__ SiteRef site_ref(const PhaseCtx& m, int32_t q, int32_t i) {
+  using P = StageShape<W, H>;
+  SiteRef r;
+  r.z = wrap_to(q, m.L);
+  const int32_t dr = i / P::PER_ROW;
+  r.ry = P::RY0 + dr;
+  r.y = wrap_to(m.y0 - W::OY + r.ry, m.L);
+  r.p = (r.y + r.z + C) & 1;
+  r.j = (i - dr * P::PER_ROW) + W::OX - ((H + r.p) >> 1);
+  r.xh = wrap_to(m.xh0 - W::OX + r.j, m.Lh);
+  return r;
+}
+
+// The six couplings of a site: +x,+y,+z bonds stored at the site (colour C planes),
+// -x,-y,-z at its other-colour neighbours.
+template <typename R>
+struct Bonds {
+  R px, mx, py, my, pz, mz;
+};
+
+template <typename R, int C>
+__device__ __forceinline__ Bonds<R> site_bonds(const R* J, const PhaseCtx& m, const SiteRef& r) {
+  const int32_t ym = r.y == 0 ? m.L - 1 : r.y - 1, zm = r.z == 0 ? m.L - 1 : r.z - 1;
+  const int32_t xhm = r.p ? r.xh : (r.xh == 0 ? m.Lh - 1 : r.xh - 1);
+  const uint32_t zo = m.zstride * (uint32_t)r.z;
+  const uint32_t own = zo + (uint32_t)m.Lh * (uint32_t)r.y + (uint32_t)r.xh;
   const R* Jo = J + (uint32_t)(3 * C) * m.Nh;
   const R* Jn = J + (uint32_t)(3 * (1 - C)) * m.Nh;
-  const R j_px = Jo[own];
-  const R j_mx = Jn[zo + (uint32_t)m.Lh * (uint32_t)y + (uint32_t)xhm];
-  const R j_py = Jo[m.Nh + own];
-  const R j_my = Jn[m.Nh + zo + (uint32_t)m.Lh * (uint32_t)ym + (uint32_t)xh];
-  const R j_pz = Jo[2 * m.Nh + own];
-  const R j_mz = Jn[2 * m.Nh + m.zstride * (uint32_t)zm + (uint32_t)m.Lh * (uint32_t)y +
-                    (uint32_t)xh];
+  Bonds<R> b;
+  b.px = Jo[own];
+  b.mx = Jn[zo + (uint32_t)m.Lh * (uint32_t)r.y + (uint32_t)xhm];
+  b.py = Jo[m.Nh + own];
+  b.my = Jn[m.Nh + zo + (uint32_t)m.Lh * (uint32_t)ym + (uint32_t)r.xh];
+  b.pz = Jo[2 * m.Nh + own];
+  b.mz = Jn[2 * m.Nh + m.zstride * (uint32_t)zm + (uint32_t)m.Lh * (uint32_t)r.y +
+            (uint32_t)r.xh];
+  return b;
+}
+
+// Stage s (colour C = s & 1 for s < 2, colour 0 for s = 2; ring NS - 1 - s, none for
+// s = 2) with a thread of the first T per site: the sites of thread threadIdx.x, one
+// per round, and their couplings, loaded a step before they are used.
+template <class W, int S, int T>
+struct Stage {
+  static constexpr int C = S == 1 ? 1 : 0;
+  static constexpr int H = S == 2 ? 0 : W::OX - S;
+  static constexpr int COUNT = StageShape<W, H>::COUNT;
+  static constexpr int ROUNDS = (COUNT + T - 1) / T;
+  __device__ __forceinline__ static bool has(int r) {
+    const int32_t i = (int32_t)threadIdx.x + r * T;
+    return (int32_t)threadIdx.x < T && (COUNT % T == 0 || i < COUNT);
+  }
+};
+
+template <typename R, class W, int S, int T>
+struct StageBonds {
+  Bonds<R> b[Stage<W, S, T>::ROUNDS];
+};
+
+template <typename R, class W, int S, int T>
+__device__ __forceinline__ void fetch_bonds(StageBonds<R, W, S, T>& sb, const R* J,
+                                            const PhaseCtx& m, int32_t q) {
+  using St = Stage<W, S, T>;
+#pragma unroll
+  for (int r = 0; r < St::ROUNDS; ++r)
+    if (St::has(r))
+      sb.b[r] = site_bonds<R, St::C>(
+          J, m, site_ref<W, St::C, St::H>(m, q, (int32_t)threadIdx.x + r * T));
+}
+
+// Update of the site of colour C at r on plane q: the field of eq. 2 from the window
+// (neighbour colour 1 - C) and the couplings jb, in the fixed order of the single-pass
+// kernel, then (optionally renormalising before or after) apply_update.  The result goes
+// back to the window when `keep`; with `own_out` the tile's sites are also written to
+// the output.
+template <typename R, class W, int C, PassMode MODE, int G>
+__device__ __forceinline__ double phase_site(R* lds, R* out, const PhaseCtx& m, int32_t q,
+                                             const SiteRef& r, const Bonds<R>& jb,
+                                             const HitCtx<R>& hc, bool renorm_before,
+                                             bool renorm_after, bool keep, bool own_out) {
+  const R* cur = slice<R, W>(lds, 1 - C, q);
+  const R* up = slice<R, W>(lds, 1 - C, q + 1);
+  const R* dn = slice<R, W>(lds, 1 - C, q - 1);
+  const int32_t j = r.j;
+  const int32_t row = r.ry * W::RX;
+  const int32_t i_px = row + (r.p ? j + 1 : j), i_mx = row + (r.p ? j : j - 1);
+  const int32_t i_py = row + W::RX + j, i_my = row - W::RX + j, i_z = row + j;
   R hcomp[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int32_t kb = k * kColour;
-    R acc = j_px * cur[kb + i_px];
-    acc = dev_fma(j_mx, cur[kb + i_mx], acc);
-    acc = dev_fma(j_py, cur[kb + i_py], acc);
-    acc = dev_fma(j_my, cur[kb + i_my], acc);
-    acc = dev_fma(j_pz, up[kb + i_z], acc);
-    acc = dev_fma(j_mz, dn[kb + i_z], acc);
+    const int32_t kb = k * W::COLOUR;
+    R acc = jb.px * cur[kb + i_px];
+    acc = dev_fma(jb.mx, cur[kb + i_mx], acc);
+    acc = dev_fma(jb.py, cur[kb + i_py], acc);
+    acc = dev_fma(jb.my, cur[kb + i_my], acc);
+    acc = dev_fma(jb.pz, up[kb + i_z], acc);
+    acc = dev_fma(jb.mz, dn[kb + i_z], acc);
     hcomp[k] = acc;
   }
   const Vec3<R> h{hcomp[0], hcomp[1], hcomp[2]};
-  R* mine = slice(lds, C, q);
-  const int32_t io = ry * kRegX + j;
-  Vec3<R> s{mine[io], mine[kColour + io], mine[2 * kColour + io]};
-  const uint32_t site = (uint32_t)(2 * xh + p) + (uint32_t)m.L * (uint32_t)(y + m.L * z);
-  const double d = apply_update<R, MODE>(s, h, site, hc);
-  mine[io] = s.x;
-  mine[kColour + io] = s.y;
-  mine[2 * kColour + io] = s.z;
+  R* mine = slice<R, W>(lds, C, q);
+  const int32_t io = row + j;
+  Vec3<R> s{mine[io], mine[W::COLOUR + io], mine[2 * W::COLOUR + io]};
+  if (renorm_before) s = unit_vector(s);
+  const uint32_t site =
+      (uint32_t)(2 * r.xh + r.p) + (uint32_t)m.L * (uint32_t)(r.y + m.L * r.z);
+  const double d = apply_update<R, MODE, G>(s, h, site, hc);
+  if (renorm_after) s = unit_vector(s);
+  if (keep) {
+    mine[io] = s.x;
+    mine[W::COLOUR + io] = s.y;
+    mine[2 * W::COLOUR + io] = s.z;
+  }
+  if (own_out && r.ry >= W::OY && r.ry < W::OY + kPTY && j >= W::OX && j < W::OX + kPTX) {
+    R* o = out + (uint32_t)(3 * C) * m.Nh + m.zstride * (uint32_t)r.z +
+           (uint32_t)m.Lh * (uint32_t)r.y + (uint32_t)r.xh;
+    o[0] = s.x;
+    o[m.Nh] = s.y;
+    o[2 * m.Nh] = s.z;
+  }
   return d;
 }
 
-// The over-relaxation phase (the one the schedule runs as one launch): no energy
-// changes to record.
-template <typename R>
-__global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
-  constexpr PassMode MODE = PassMode::OverRelax;
-  __shared__ R lds[2 * kRing * kSlice];
-  const int32_t tiles_x = a.L / 2 / kPTX, tiles_y = a.L / kPTY;
+// Every site of stage s on plane q, with the couplings fetched for it (sb), or with
+// PRE false loading each site's couplings just before its update (fewer registers).
+template <typename R, class W, int S, PassMode MODE, int G, int T, bool PRE>
+__device__ __forceinline__ double stage(R* lds, const R* J, R* out, const PhaseCtx& m,
+                                        int32_t q, const StageBonds<R, W, S, T>& sb,
+                                        const HitCtx<R>& hc, bool renorm_before,
+                                        bool renorm_after, bool keep, bool own_out) {
+  using St = Stage<W, S, T>;
+  double d = 0.0;
+#pragma unroll
+  for (int r = 0; r < St::ROUNDS; ++r) {
+    if (St::has(r)) {
+      const SiteRef ref = site_ref<W, St::C, St::H>(m, q, (int32_t)threadIdx.x + r * T);
+      const Bonds<R> jb = PRE ? sb.b[r] : site_bonds<R, St::C>(J, m, ref);
+      d += phase_site<R, W, St::C, MODE, G>(lds, out, m, q, ref, jb, hc, renorm_before,
+                                            renorm_after, keep, own_out);
+    }
+  }
+  return d;
+}
+
+__device__ __forceinline__ PhaseCtx phase_ctx(int32_t L, int32_t zp) {
+  const int32_t tiles_x = L / 2 / kPTX, tiles_y = L / kPTY;
   const int32_t tile = xcd_tile((int32_t)blockIdx.x, (int32_t)gridDim.x);
   const int32_t tx = tile % tiles_x;
   const int32_t rest = tile / tiles_x;
   const int32_t ty = rest % tiles_y, tz = rest / tiles_y;
   PhaseCtx m;
-  m.L = a.L;
-  m.Lh = a.L / 2;
-  m.zstride = (uint32_t)m.Lh * (uint32_t)a.L;
-  m.Nh = m.zstride * (uint32_t)a.L;
+  m.L = L;
+  m.Lh = L / 2;
+  m.zstride = (uint32_t)m.Lh * (uint32_t)L;
+  m.Nh = m.zstride * (uint32_t)L;
   m.xh0 = tx * kPTX;
   m.y0 = ty * kPTY;
-  m.z0 = tz * kPZ;
+  m.z0 = tz * zp;
+  return m;
+}
+
+// Before step 0 (stage A on plane z0 - NS + 1): colour 1 of planes z0 - NS .. z0 - NS
+// + 2 and colour 0 of plane z0 - NS + 1 in LDS; in registers the slices the end of step
+// 0 puts in place.
+template <typename R, class W, int NS>
+__device__ __forceinline__ void prologue(R* lds, SliceRegs<R, W>& r0, SliceRegs<R, W>& r1,
+                                         const SliceOffsets<W>& so, const R* in,
+                                         const PhaseCtx& m) {
+  for (int32_t q = m.z0 - NS; q <= m.z0 - NS + 2; ++q) {
+    fetch<R, W>(r1, so, in, m, 1, q);
+    put<R, W>(lds, r1, 1, q);
+  }
+  fetch<R, W>(r0, so, in, m, 0, m.z0 - NS + 1);
+  put<R, W>(lds, r0, 0, m.z0 - NS + 1);
+  fetch<R, W>(r0, so, in, m, 0, m.z0 - NS + 2);
+  fetch<R, W>(r1, so, in, m, 1, m.z0 - NS + 3);
+}
+
+// NS = 2: the over-relaxation phase.  NS = 3: the phase, then the colour-0 pass of the
+// next sweep's Monte Carlo phase in mode MC.
+template <typename R, int NS, PassMode MC>
+__global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
+  using W = typename std::conditional<NS == 2, WinPhase, WinMc>::type;
+  constexpr PassMode OR = PassMode::OverRelax;
+  constexpr int T = kPhaseThreads;
+  constexpr int STEPS = kPZ + 2 * (NS - 1);
+  __shared__ R lds[(W::K0 + W::K1) * W::SLICE];
+  const PhaseCtx m = phase_ctx(a.L, kPZ);
   const HitCtx<R> hc{a.beta, a.sweep, a.phase, a.k_hits, a.seed_lo, a.seed_hi};
+  const HitCtx<R> hm{a.beta, a.mc_sweep, 0u, a.k_hits, a.seed_lo, a.seed_hi};
+  const bool rn = NS == 3 && a.renorm != 0;
+  SliceOffsets<W> so;
+  slice_offsets<W>(so, m);
+  SliceRegs<R, W> r0, r1;
+  prologue<R, W, NS>(lds, r0, r1, so, a.in, m);
+  // The phase alone loads the couplings of its stages' sites a step ahead (the loads
+  // stay in flight across the barriers).  With stage C each site's are loaded just
+  // before its update: holding them across stage C would cost the registers of the
+  // second workgroup per compute unit, which measures slower.
+  constexpr bool PF = NS == 2;
+  StageBonds<R, W, 0, T> bA;
+  StageBonds<R, W, 1, T> bB;
+  StageBonds<R, W, 2, T> none;
+  if (PF) fetch_bonds<R, W, 0, T>(bA, a.J, m, m.z0 - 1);
 
-  // before step 0 (stage A on plane z0 - 1): colour 1 of planes z0 - 2 .. z0, colour 0
-  // of plane z0 - 1; in registers the slices the end of step 0 puts in place
-  SliceOffsets so;
-  slice_offsets(so, m);
-  SliceRegs<R> r0, r1;
-  for (int32_t q = m.z0 - 2; q <= m.z0; ++q) {
-    fetch<R>(r1, so, a.in, m, 1, q);
-    put<R>(lds, r1, 1, q);
-  }
-  fetch<R>(r0, so, a.in, m, 0, m.z0 - 1);
-  put<R>(lds, r0, 0, m.z0 - 1);
-  fetch<R>(r0, so, a.in, m, 0, m.z0);
-  fetch<R>(r1, so, a.in, m, 1, m.z0 + 1);
-
-  for (int32_t t = 0; t <= kPZ + 1; ++t) {
-    const int32_t q = m.z0 - 1 + t;  // stage A plane; stage B works on q - 1
+  double dE = 0.0;
+  for (int32_t t = 0; t < STEPS; ++t) {
+    const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
     __syncthreads();
-    {
-      const int32_t z = wrap_to(q, m.L);
-#pragma unroll
-      for (int r = 0; r < kARounds; ++r) {
-        const int32_t i = (int32_t)threadIdx.x + r * kPhaseThreads;
-        if (i < kASites) {
-          const int32_t dr = i / (kPTX + 1);
-          const int32_t ry = 1 + dr;
-          const int32_t y = wrap_to(m.y0 - 2 + ry, m.L);
-          const int32_t p0 = (y + z) & 1;
-          const int32_t j = (i - dr * (kPTX + 1)) + (1 - p0);
-          phase_site<R, 0, MODE>(lds, a.J, m, q, z, ry, j, hc);
-        }
+    stage<R, W, 0, OR, 1, T, PF>(lds, a.J, a.out, m, q, bA, hc, false, false, true, false);
+    if (PF && t + 1 < STEPS) fetch_bonds<R, W, 0, T>(bA, a.J, m, q + 1);
+    if (PF && t == 1) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
+    __syncthreads();
+    if constexpr (NS == 2) {
+      if (t >= 2) {
+        stage<R, W, 1, OR, 1, T, true>(lds, a.J, a.out, m, q - 1, bB, hc, false, false, true,
+                                       false);
+        if (t + 1 < STEPS) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
+        __syncthreads();
       }
-    }
-    __syncthreads();
-    if (t >= 2) {
-      const int32_t b = q - 1;
-      const int32_t z = wrap_to(b, m.L);
+      // colour 0 of plane q + 1 replaces plane q - 2 (last read by stage B)
+      if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
+      if (t >= 2) {
+        // plane b = q - 1 is final: write the tile's sites of both colours
+        const int32_t b = q - 1;
+        const uint32_t zo = m.zstride * (uint32_t)wrap_to(b, m.L);
+        constexpr int kStore = 2 * 3 * kPTY * kPTX;
 #pragma unroll
-      for (int r = 0; r < kBRounds; ++r) {
-        const int32_t i = (int32_t)threadIdx.x + r * kPhaseThreads;
-        if (i < kBSites) {
-          const int32_t dr = i / kPTX;
-          phase_site<R, 1, MODE>(lds, a.J, m, b, z, 2 + dr, 1 + (i - dr * kPTX), hc);
+        for (int r = 0; r < (kStore + T - 1) / T; ++r) {
+          const int32_t e = (int32_t)threadIdx.x + r * T;
+          if (e < kStore) {
+            const int32_t col = e % kPTX;
+            const int32_t rest2 = e / kPTX;
+            const int32_t iy = rest2 % kPTY;
+            const int32_t cc = rest2 / kPTY;  // 3 * colour + component
+            const int32_t c = cc / 3, comp = cc - 3 * c;
+            const R v = slice<R, W>(lds, c, b)[comp * W::COLOUR + (W::OY + iy) * W::RX +
+                                               W::OX + col];
+            a.out[(uint32_t)cc * m.Nh + zo + (uint32_t)m.Lh * (uint32_t)(m.y0 + iy) +
+                  (uint32_t)(m.xh0 + col)] = v;
+          }
         }
+        __syncthreads();
+      }
+    } else {
+      if (t >= 2) {
+        // colour 1 of plane q - 1 is final after stage B: its tile goes out from there
+        const bool own = q - 1 >= m.z0 && q - 1 < m.z0 + kPZ;
+        stage<R, W, 1, OR, 1, T, false>(lds, a.J, a.out, m, q - 1, bB, hc, false, rn, true,
+                                        own);
       }
       __syncthreads();
-    }
-    // colour 0 of plane q + 1 replaces plane q - 2 (last read by stage B)
-    if (t <= kPZ) put<R>(lds, r0, 0, q + 1);
-    if (t >= 2) {
-      // plane b = q - 1 is final: write the tile's sites of both colours
-      const int32_t b = q - 1;
-      const uint32_t zo = m.zstride * (uint32_t)wrap_to(b, m.L);
-#pragma unroll
-      for (int r = 0; r < kStoreRounds; ++r) {
-        const int32_t e = (int32_t)threadIdx.x + r * kPhaseThreads;
-        if (e < kStore) {
-          const int32_t col = e % kPTX;
-          const int32_t rest2 = e / kPTX;
-          const int32_t iy = rest2 % kPTY;
-          const int32_t cc = rest2 / kPTY;  // 3 * colour + component
-          const int32_t c = cc / 3, comp = cc - 3 * c;
-          const R v = slice(lds, c, b)[comp * kColour + (2 + iy) * kRegX + 1 + col];
-          a.out[(uint32_t)cc * m.Nh + zo + (uint32_t)m.Lh * (uint32_t)(m.y0 + iy) +
-                (uint32_t)(m.xh0 + col)] = v;
-        }
-      }
+      // colour 0 of plane q - 2 (one of the tile's own planes) after stage C is final
+      if (t >= 4)
+        dE += stage<R, W, 2, MC, kHitGroup, T, false>(lds, a.J, a.out, m, q - 2, none, hm, rn,
+                                                      false, false, true);
       __syncthreads();
+      // colour 0 of plane q + 1 replaces plane q - 2, read by stage C above
+      if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
     }
-    // colour 1 of plane q + 2 replaces plane q - 1 (stored above)
-    if (t <= kPZ) {
-      put<R>(lds, r1, 1, q + 2);
-      if (t + 1 <= kPZ) {
-        fetch<R>(r0, so, a.in, m, 0, q + 2);
-        fetch<R>(r1, so, a.in, m, 1, q + 3);
+    // colour 1 of plane q + 2 replaces plane q + 2 - K1 (last read this step)
+    if (t < STEPS - 1) {
+      put<R, W>(lds, r1, 1, q + 2);
+      if (t < STEPS - 2) {
+        fetch<R, W>(r0, so, a.in, m, 0, q + 2);
+        fetch<R, W>(r1, so, a.in, m, 1, q + 3);
       }
     }
   }
+  if constexpr (NS == 3) {
+    __shared__ double s_red[16];
+    const double total = block_sum(dE, s_red);
+    if (threadIdx.x == 0) a.partials[blockIdx.x] += total;
+  }
+}
+
+template <typename R, int NS, PassMode MC>
+hipError_t launch_ns(const PhaseArgs<R>& a, hipStream_t st) {
+  const dim3 grid((unsigned)phase_blocks(a.L)), block(kPhaseThreads);
+  hipLaunchKernelGGL((phase_kernel<R, NS, MC>), grid, block, 0, st, a);
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -263,9 +435,12 @@ int32_t phase_blocks(int32_t L) { return (L / 2 / kPTX) * (L / kPTY) * (L / kPZ)
 template <typename R>
 hipError_t launch_phase(const PhaseArgs<R>& a, hipStream_t st) {
   if (!phase_supported(a.L)) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)phase_blocks(a.L)), block(kPhaseThreads);
-  hipLaunchKernelGGL(phase_kernel<R>, grid, block, 0, st, a);
-  return hipGetLastError();
+  if (!a.then_mc) return launch_ns<R, 2, PassMode::OverRelax>(a, st);
+  if (!a.partials) return hipErrorInvalidValue;
+  if ((PassMode)a.mc_mode == PassMode::Metropolis)
+    return launch_ns<R, 3, PassMode::Metropolis>(a, st);
+  if ((PassMode)a.mc_mode == PassMode::HeatBath) return launch_ns<R, 3, PassMode::HeatBath>(a, st);
+  return hipErrorInvalidValue;
 }
 
 template hipError_t launch_phase<float>(const PhaseArgs<float>&, hipStream_t);

@@ -8,6 +8,7 @@ import os
 import re
 
 import numpy as np
+import torch
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -86,7 +87,7 @@ def test_null_and_missing_buffers_rejected(hsg):
     (1.0, 70000, 0, 0, 0, 1),
     # HSG_MARCH_PHASE without HSG_FUSED; HSG_FUSED with a pass-by-pass variant
     (1.0, 1, 0, 0, 16, 1), (1.0, 1, 0, 0, 4 | 32, 1), (1.0, 1, 0, 0, 4 | 64, 1),
-    (1.0, 1, 0, 0, 4 | 128, 1), (1.0, 1, 0, 0, 256, 1)])
+    (1.0, 1, 0, 0, 4 | 128, 1), (1.0, 1, 0, 0, 4 | 256, 1), (1.0, 1, 0, 0, 1024, 1)])
 def test_sweep_rejects_bad_params(hsg, T, k, n_or, R, flags, n):
     lib = hsg.lib()
     d = _desc(hsg)
@@ -114,6 +115,9 @@ def test_phase_launch_needs_the_larger_work_buffer(hsg):
     p = hsg._SweepParams(1.0, 1, 1, 0, hsg.HSG_PHASE_LAUNCH)
     assert lib.hsg_sweep(ctypes.byref(d), ctypes.byref(p), 1, None) == -1
     assert b"HSG_PHASE_LAUNCH" in lib.hsg_last_error()
+    p = hsg._SweepParams(1.0, 1, 1, 0, hsg.HSG_PHASE_MC)
+    assert lib.hsg_sweep(ctypes.byref(d), ctypes.byref(p), 2, None) == -1
+    assert b"HSG_PHASE_MC" in lib.hsg_last_error()
     assert hsg.phase_supported(64) and not hsg.phase_supported(96)
 
 
@@ -223,3 +227,15 @@ def test_pt_workload_shape():
     assert len({(s.J_group, s.L) for s in specs}) == 256
 
 
+
+
+def test_default_flags(hsg):
+    """Phase launches only where the lattice gives them enough workgroups; in binary32 the
+    phase launch also carries the next colour-0 Monte Carlo pass (measured faster), in
+    binary64 not (measured slower)."""
+    assert hsg.default_flags(256, torch.float32) == hsg.HSG_SNAKE | hsg.HSG_PHASE_MC
+    assert hsg.default_flags(512) == hsg.HSG_SNAKE | hsg.HSG_PHASE_MC
+    assert hsg.default_flags(256, torch.float64) == hsg.HSG_SNAKE | hsg.HSG_PHASE_LAUNCH
+    assert hsg.default_flags(128, torch.float32) == hsg.HSG_SNAKE
+    assert hsg.default_flags(320) == hsg.HSG_SNAKE | hsg.HSG_PHASE_MC
+    assert hsg.default_flags(288) == hsg.HSG_SNAKE  # not a multiple of 64

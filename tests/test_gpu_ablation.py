@@ -26,7 +26,8 @@ def variants(m):
     return {"TEXT": m.HSG_SNAKE | m.HSG_STREAM_LOADS, "TEXT-plain": m.HSG_STREAM_LOADS,
             "CA": m.HSG_PLANE_LAUNCH, "CA+S": m.HSG_PLANE_LAUNCH | m.HSG_SNAKE,
             "SM": m.HSG_FUSED | m.HSG_MARCH_PHASE, "SM4P": m.HSG_FUSED,
-            "PHASE": m.HSG_SNAKE | m.HSG_PHASE_LAUNCH, "PHASE-plain": m.HSG_PHASE_LAUNCH}
+            "PHASE": m.HSG_SNAKE | m.HSG_PHASE_LAUNCH, "PHASE-plain": m.HSG_PHASE_LAUNCH,
+            "PHASE-MC": m.HSG_SNAKE | m.HSG_PHASE_MC, "PHASE-MC-plain": m.HSG_PHASE_MC}
 
 
 def run(m, L, dtype, flags, *, k, n_or, R, n, hb=False, T=0.4):
@@ -43,6 +44,10 @@ def run(m, L, dtype, flags, *, k, n_or, R, n, hb=False, T=0.4):
     (256, torch.float32, 4, 1, 10, 2, False),
     (256, torch.float32, 0, 2, 1, 2, False),
     (256, torch.float64, 2, 1, 1, 2, True),
+    # renormalisation inside and outside the launches that carry a Monte Carlo pass
+    (64, torch.float32, 4, 2, 1, 4, False),
+    (128, torch.float64, 2, 1, 3, 4, False),
+    (256, torch.float32, 4, 1, 2, 5, False),
 ])
 def test_variants_equal_default_schedule(hsg, L, dtype, k, n_or, R, n, hb):
     ref_s, ref_E = run(hsg, L, dtype, 0, k=k, n_or=n_or, R=R, n=n, hb=hb)
@@ -51,7 +56,7 @@ def test_variants_equal_default_schedule(hsg, L, dtype, k, n_or, R, n, hb):
             continue
         s, E = run(hsg, L, dtype, flags, k=k, n_or=n_or, R=R, n=n, hb=hb)
         assert torch.equal(s, ref_s), name
-        if flags & hsg.HSG_FUSED:
+        if flags & (hsg.HSG_FUSED | hsg.HSG_PHASE_MC):
             assert E == pytest.approx(ref_E, rel=1e-12), name  # summed in another order
         else:
             assert E == ref_E, name
@@ -71,3 +76,35 @@ def test_pass_by_pass_variants_match_oracle(hsg, name):
     ok = taint == 0
     assert ok.sum() >= 0.99 * L ** 3
     assert np.abs(got[:, ok] - s[:, ok]).max() <= 1e-5
+
+
+@pytest.mark.parametrize("dtype,hb,R,n", [(np.float32, False, 1, 2), (np.float64, False, 1, 2),
+                                          (np.float64, True, 2, 3), (np.float64, True, 0, 3)])
+def test_phase_with_monte_carlo_pass_matches_oracle(hsg, dtype, hb, R, n):
+    """HSG_PHASE_MC straight against the oracle at L = 64: every sweep but the last ends
+    with a launch that also runs the next sweep's colour-0 pass (and the renormalisation
+    due between them).  Metropolis runs two sweeps, so that the sites tainted by
+    decisions within 1e-6 of their threshold stay below 1%; heat bath makes no such
+    decisions and runs three, in binary64 (binary32 heat-bath draws go through library
+    logarithms that may differ from the host's by an ulp, which later sweeps amplify; the
+    binary32 draws are checked pass by pass against the oracle elsewhere, and the launch
+    against the pass-by-pass schedule bit for bit above)."""
+    L, seed = 64, 5
+    tdt = torch.float32 if dtype == np.float32 else torch.float64
+    spins, J = inputs.random_state(L, 43, dtype)
+    lat = hsg.Lattice(L, tdt, seed=seed, init=None)
+    lat.load(torch.from_numpy(spins), torch.from_numpy(J))
+    E0 = lat.energy().item()
+    lat.sweep(T=0.5, k=3, n_or=1, renorm_every=R, n_sweeps=n, heat_bath=hb,
+              flags=hsg.HSG_SNAKE | hsg.HSG_PHASE_MC)
+    got = lat.export()[0].cpu().numpy()
+    s = spins.copy()
+    taint = np.zeros(L ** 3, dtype=np.uint8)
+    r = O.sweep(L, seed, s, J, T=0.5, k=3, n_or=1, renorm_every=R, n_sweeps=n, E=E0,
+                heat_bath=hb, taint=taint)
+    ok = taint == 0
+    assert ok.sum() >= 0.99 * L ** 3
+    tol = 1e-5 if dtype == np.float32 else 1e-12
+    assert np.abs(got[:, ok] - s[:, ok]).max() <= tol
+    if r["n_flagged"] == 0:
+        assert abs(lat.energy().item() - r["E"]) <= tol * abs(r["E"])
