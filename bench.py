@@ -209,6 +209,11 @@ def measured_traffic(name: str):
     return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
 
 
+def note(msg: str) -> None:
+    """A progress line on stderr (the JSON result is the last line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def time_sweeps(lat, torch, *, T, k, n_or, R, steps, warmup, flags=0):
     """Average ms per sweep over `steps` sweeps, HIP events on the launch stream."""
     lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=warmup, flags=flags)
@@ -452,6 +457,7 @@ def main():
                          "site_sweeps_per_ns": N / (ms * 1e6),
                          "hbm_frac_36B": N * (1 + args.n_or) * BYTES_PER_SITE_PHASE /
                          (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+        note(f"k={k}: {upd:.1f} spin updates/ns (flags {flags})")
 
     # The Metropolis colour pass (half the sites, k hits each): its average duration from
     # Metropolis-only sweeps (two passes each, one energy fold per call) timed with events
@@ -530,20 +536,27 @@ def main():
                                   f"{args.n_or} over-relaxation, renormalise every {R}",
                       "L": L, "k": args.k, "n_or": args.n_or, "T": args.T, "flags": flags},
            "per_k": per_k, "roofline": roofline}
+    note(f"roofline: {roofline['kernel']} {roofline['kernel_ms'] * 1e3:.1f} us, "
+         f"frac {roofline['frac']:.3f}")
     if not args.no_binary64:
         rec["binary64"] = binary64_leg(hsg, args, torch, flags if args.flags is not None
                                        else hsg.default_flags(L, torch.float64))
+        note("binary64 leg done")
     if not args.no_observables:
         rec["observables"] = observables_leg(hsg, lat, torch, args.steps)
+        note("observables leg done")
     if args.batch_cycles > 0:
         del lat
         torch.cuda.empty_cache()
         rec["batched"] = batched_leg(args, torch)
+        note("batched leg done")
     if args.serve_requests > 0:
         torch.cuda.empty_cache()
         rec["served"] = served_leg(args, torch)
+        note("served leg done")
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(args)
+        note("cpu baseline done")
     print(json.dumps(rec), flush=True)
 
 
