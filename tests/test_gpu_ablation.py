@@ -108,3 +108,16 @@ def test_phase_with_monte_carlo_pass_matches_oracle(hsg, dtype, hb, R, n):
     assert np.abs(got[:, ok] - s[:, ok]).max() <= tol
     if r["n_flagged"] == 0:
         assert abs(lat.energy().item() - r["E"]) <= tol * abs(r["E"])
+
+
+def test_phase_with_monte_carlo_pass_large_lattice(hsg):
+    """HSG_PHASE_MC at L = 512 (4096 workgroups per launch) against the pass-by-pass
+    schedule: six sweeps, renormalisation due after sweeps 1 and 3 (inside launches) and
+    after sweep 5, the call's last."""
+    L = 512
+    ref_s, ref_E = run(hsg, L, torch.float32, hsg.HSG_SNAKE, k=2, n_or=1, R=2, n=6)
+    s, E = run(hsg, L, torch.float32, hsg.HSG_SNAKE | hsg.HSG_PHASE_MC, k=2, n_or=1, R=2, n=6)
+    assert torch.equal(s, ref_s)
+    assert E == pytest.approx(ref_E, rel=1e-12)
+    del ref_s, s
+    torch.cuda.empty_cache()
