@@ -350,41 +350,25 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   for (int32_t t = 0; t < STEPS; ++t) {
     const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
     __syncthreads();
-    stage<R, W, 0, OR, 1, T, PF>(lds, a.J, a.out, m, q, bA, hc, false, false, true, false);
+    // the phase alone: colour 0 of plane q is final after stage A, its tile goes out
+    // from there
+    const bool own_a = NS == 2 && q >= m.z0 && q < m.z0 + kPZ;
+    stage<R, W, 0, OR, 1, T, PF>(lds, a.J, a.out, m, q, bA, hc, false, false, true, own_a);
     if (PF && t + 1 < STEPS) fetch_bonds<R, W, 0, T>(bA, a.J, m, q + 1);
     if (PF && t == 1) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
     __syncthreads();
     if constexpr (NS == 2) {
       if (t >= 2) {
-        stage<R, W, 1, OR, 1, T, true>(lds, a.J, a.out, m, q - 1, bB, hc, false, false, true,
-                                       false);
+        // colour 1 of plane q - 1 is final after stage B and read by no later stage: its
+        // tile goes out from there, nothing back to the window
+        const bool own = q - 1 >= m.z0 && q - 1 < m.z0 + kPZ;
+        stage<R, W, 1, OR, 1, T, true>(lds, a.J, a.out, m, q - 1, bB, hc, false, false, false,
+                                       own);
         if (t + 1 < STEPS) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
-        __syncthreads();
       }
+      __syncthreads();
       // colour 0 of plane q + 1 replaces plane q - 2 (last read by stage B)
       if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
-      if (t >= 2) {
-        // plane b = q - 1 is final: write the tile's sites of both colours
-        const int32_t b = q - 1;
-        const uint32_t zo = m.zstride * (uint32_t)wrap_to(b, m.L);
-        constexpr int kStore = 2 * 3 * kPTY * kPTX;
-#pragma unroll
-        for (int r = 0; r < (kStore + T - 1) / T; ++r) {
-          const int32_t e = (int32_t)threadIdx.x + r * T;
-          if (e < kStore) {
-            const int32_t col = e % kPTX;
-            const int32_t rest2 = e / kPTX;
-            const int32_t iy = rest2 % kPTY;
-            const int32_t cc = rest2 / kPTY;  // 3 * colour + component
-            const int32_t c = cc / 3, comp = cc - 3 * c;
-            const R v = slice<R, W>(lds, c, b)[comp * W::COLOUR + (W::OY + iy) * W::RX +
-                                               W::OX + col];
-            a.out[(uint32_t)cc * m.Nh + zo + (uint32_t)m.Lh * (uint32_t)(m.y0 + iy) +
-                  (uint32_t)(m.xh0 + col)] = v;
-          }
-        }
-        __syncthreads();
-      }
     } else {
       if (t >= 2) {
         // colour 1 of plane q - 1 is final after stage B: its tile goes out from there
