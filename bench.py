@@ -51,6 +51,26 @@ OPS_PER_SITE_OR = 21 + 3 + 2 + 1 + 6
 def ops_per_site_pass(k: int) -> int:
     """Algorithmic lane operations of one site's Metropolis update with k hits."""
     return OPS_PER_SITE + OPS_PER_HIT * k + OPS_PER_BLOCK * ((3 * k + 3) // 4)
+
+
+# Heat-bath draw (exact sample of exp(beta sigma.h) on the sphere), each library
+# function (expm1, log1p or log, square root, division) counted as one operation:
+#   two uniforms 2 x (shift-in, subtract)                                = 4
+#   |h|: h.h (3), root, a = beta |h|, a > 0                              = 6
+#   cosine to the field: 1 - u0, -2a, expm1, w q (2), w q <= 1/2,
+#     log1p or log (3), divide, add, two clamps (4)                      = 15
+#   rho = sqrt(1 - c^2) (2), azimuth as the Metropolis trial point (20) = 22
+#   frame about h/|h|: h.h > 0, three divisions, sign (2), -1/(sgn + n_z)
+#     (2), b (2), e1 (6), e2 (3)                                         = 19
+#   point: rho cos, rho sin, three components x (mul, fma, fma)          = 11
+#   energy change and sum: trial.h (3), dE, convert, add                = 6
+# A draw takes two of a block's four words: k draws draw ceil(k / 2) blocks.
+OPS_PER_DRAW = 4 + 6 + 15 + 22 + 19 + 11 + 6
+
+
+def ops_per_site_heat_bath(k: int) -> int:
+    """Algorithmic lane operations of one site's heat-bath update with k draws."""
+    return OPS_PER_SITE + OPS_PER_DRAW * k + OPS_PER_BLOCK * ((k + 1) // 2)
 _COMMON_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/csrc/hsg_device.h",
                    "paper_1006_2566_amd/csrc/hsg_internal.h")
 # The kernels that can dominate the headline sweep: the binary32 Metropolis colour pass,
@@ -108,6 +128,8 @@ def parse():
                     help="use the library defaults instead of timing candidate launch shapes")
     ap.add_argument("--no-binary64", action="store_true",
                     help="skip timing the headline sweep with binary64 spins")
+    ap.add_argument("--no-heat-bath", action="store_true",
+                    help="skip timing the headline sweep with heat-bath draws")
     ap.add_argument("--no-observables", action="store_true",
                     help="skip timing the Fourier-overlap records (chi_SG, xi inputs)")
     ap.add_argument("--counters", action="store_true",
@@ -241,6 +263,26 @@ def binary64_leg(hsg, args, torch, flags):
     torch.cuda.empty_cache()
     return {"dtype": "f64", "steps": steps, "ms_per_step": ms, "flags": flags,
             "spin_updates_per_ns": L ** 3 * (args.k + args.n_or) / (ms * 1e6)}
+
+
+def heat_bath_leg(hsg, lat, torch, args, flags, pass_flags):
+    """The headline sweep with k heat-bath draws per site in place of the Metropolis
+    hits (same traversal), and the heat-bath colour pass alone against the vector-ALU
+    roofline (Metropolis-free sweeps, two passes each, events on the launch stream)."""
+    N = lat.L ** 3
+    steps = max(10, args.steps // 2)
+    ms = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=args.renorm_every,
+                     steps=steps, warmup=2, flags=flags | hsg.HSG_HEAT_BATH)
+    ms_pass = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=steps, warmup=2,
+                          flags=pass_flags | hsg.HSG_HEAT_BATH) / 2.0
+    ops = N / 2 * ops_per_site_heat_bath(args.k)
+    tops = ops / (ms_pass * 1e-3) / 1e12
+    return {"k_draws": args.k, "steps": steps, "ms_per_step": ms, "flags": flags | hsg.HSG_HEAT_BATH,
+            "spin_updates_per_ns": N * (args.k + args.n_or) / (ms * 1e6),
+            "pass": {"kernel": "colour_pass_kernel<float, HeatBath>", "bound": "alu",
+                     "kernel_ms": ms_pass, "ops_per_launch": ops, "achieved": tops,
+                     "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": tops / ALU_PEAK_TOPS,
+                     "draws_per_ns": N / 2 * args.k / (ms_pass * 1e6)}}
 
 
 def observables_leg(hsg, lat, torch, steps):
@@ -542,6 +584,9 @@ def main():
         rec["binary64"] = binary64_leg(hsg, args, torch, flags if args.flags is not None
                                        else hsg.default_flags(L, torch.float64))
         note("binary64 leg done")
+    if not args.no_heat_bath:
+        rec["heat_bath"] = heat_bath_leg(hsg, lat, torch, args, flags, pass_flags)
+        note("heat-bath leg done")
     if not args.no_observables:
         rec["observables"] = observables_leg(hsg, lat, torch, args.steps)
         note("observables leg done")
