@@ -7,9 +7,9 @@
 // marches through z holding, in LDS, a few planes of each colour of its region.  With NS
 // stages (2: the phase; 3: the phase and the Monte Carlo pass) stage s updates its
 // colour on the tile and a ring of NS - 1 - s sites around it, so that the next stage
-// finds every neighbour it reads already updated; the region is the tile widened by NS
-// sites on each side (NS - 1 colour columns in x, NS rows in y).  With a = z0 - (NS - 1)
-// + t the plane of stage A at step t:
+// finds every neighbour it reads already updated; the region is the tile widened on each
+// side by NS - 1 colour columns in x and NS rows in y.  With a = z0 - (NS - 1) + t the
+// plane of stage A at step t:
 //
 //   stage A   colour 0, over-relaxation, ring NS - 1, plane a
 //   stage B   colour 1, over-relaxation, ring NS - 2, plane a - 1 (reads colour 0 on
@@ -20,7 +20,9 @@
 // The ring and the planes outside the tile's own belong to other workgroups, which
 // compute them too, from the same inputs and the same Philox draws, hence to the same
 // bits; so workgroups never communicate.  They read the spins before the launch from one
-// buffer and write the tile after it to another.  Stage C runs on the tile only: the
+// buffer and write the tile after it to another, each site from registers after its
+// last stage (colour 1 after stage B; colour 0 after stage A, or stage C when the launch
+// carries the Monte Carlo pass).  Stage C runs on the tile only: the
 // expensive Monte Carlo update is never recomputed, and the phase's spin traffic (the
 // planes in LDS) serves the Monte Carlo pass too.
 //
