@@ -55,8 +55,8 @@ extern "C" {
 #define HSG_L_MAX 1290 /* largest L: N = L^3 < 2^31 keeps every site index in 32 bits */
 
 /* Sweep flags (hsg_sweep_params.flags).  HSG_SNAKE, HSG_FUSED and the variants below
- * change the order in which memory is touched, never a spin; with HSG_FUSED the binary64
- * energy changes are summed in another (still fixed) order. */
+ * change the order in which memory is touched, never a spin; with HSG_FUSED and
+ * HSG_PHASE_MC the binary64 energy changes are summed in another (still fixed) order. */
 #define HSG_HEAT_BATH 1 /* the Monte Carlo phase uses heat-bath draws instead of Metropolis */
 #define HSG_SNAKE 2     /* successive colour passes walk the lattice in opposite z order */
 #define HSG_FUSED 4     /* run up to four consecutive colour passes per launch (binary32;
