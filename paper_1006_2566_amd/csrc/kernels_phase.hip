@@ -183,8 +183,9 @@ __device__ __forceinline__ Bonds<R> site_bonds(const R* J, const PhaseCtx& m, co
 }
 
 // Stage s (colour C = s & 1 for s < 2, colour 0 for s = 2; ring NS - 1 - s, none for
-// s = 2) with a thread of the first T per site: the sites of thread threadIdx.x, one
-// per round, and their couplings, loaded a step before they are used.
+// s = 2) with a thread of the first T per site: thread threadIdx.x takes one site per
+// round.  StageBonds holds the couplings of a thread's sites when they are loaded ahead
+// of the stage.
 template <class W, int S, int T>
 struct Stage {
   static constexpr int C = S == 1 ? 1 : 0;
