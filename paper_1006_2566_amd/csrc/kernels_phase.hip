@@ -24,7 +24,9 @@
 // last stage (colour 1 after stage B; colour 0 after stage A, or stage C when the launch
 // carries the Monte Carlo pass).  Stage C runs on the tile only: the
 // expensive Monte Carlo update is never recomputed, and the phase's spin traffic (the
-// planes in LDS) serves the Monte Carlo pass too.
+// planes in LDS) serves the Monte Carlo pass too, as do the +x,+y,+z couplings stage A
+// loads for the tile's sites: stage A takes those sites first, each thread the one it
+// will update in stage C two steps later, and keeps their three couplings.
 //
 // The site arithmetic (field of eq. 2 in the fixed order of the single-pass kernel, then
 // the reflection of §4 or the k Metropolis hits / heat-bath draws) is the single pass's,
@@ -152,6 +154,35 @@ __device__ __forceinline__ SiteRef site_ref(const PhaseCtx& m, int32_t q, int32_
   r.y = wrap_to(m.y0 - W::OY + r.ry, m.L);
   r.p = (r.y + r.z + C) & 1;
   r.j = (i - dr * P::PER_ROW) + W::OX - ((H + r.p) >> 1);
+  r.xh = wrap_to(m.xh0 - W::OX + r.j, m.Lh);
+  return r;
+}
+
+// Site i of stage A with stage C behind it (NS = 3): the tile's sites first, in stage
+// C's order (site i < kPTX * kPTY sits where stage C's site i does), then the ring of two
+// sites: the two rows above and below the tile, then its first and last columns.
+template <class W>
+__device__ __forceinline__ SiteRef site_ref_a3(const PhaseCtx& m, int32_t q, int32_t i) {
+  constexpr int PER = kPTX + 2;  // ring-2 row: 34 colour sites, columns 1 .. 34
+  SiteRef r;
+  r.z = wrap_to(q, m.L);
+  if (i < kPTX * kPTY) {
+    r.ry = W::OY + i / kPTX;
+    r.j = W::OX + i % kPTX;
+  } else {
+    const int32_t k = i - kPTX * kPTY;
+    if (k < 4 * PER) {
+      const int32_t row = k / PER;  // 0, 1: above the tile; 2, 3: below it
+      r.ry = row < 2 ? 1 + row : W::OY + kPTY + row - 2;
+      r.j = 1 + (k - row * PER);
+    } else {
+      const int32_t e = k - 4 * PER;
+      r.ry = W::OY + (e >> 1);
+      r.j = (e & 1) ? PER : 1;
+    }
+  }
+  r.y = wrap_to(m.y0 - W::OY + r.ry, m.L);
+  r.p = (r.y + r.z) & 1;
   r.xh = wrap_to(m.xh0 - W::OX + r.j, m.Lh);
   return r;
 }
@@ -341,22 +372,42 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   prologue<R, W, NS>(lds, r0, r1, so, a.in, m);
   // The phase alone loads the couplings of its stages' sites a step ahead (the loads
   // stay in flight across the barriers).  With stage C each site's are loaded just
-  // before its update: holding them across stage C would cost the registers of the
-  // second workgroup per compute unit, which measures slower.
+  // before its update (holding them across stage C would cost the registers of the
+  // second workgroup per compute unit, which measures slower) -- except the three a
+  // tile site's stage C takes from stage A, which loaded them two steps earlier.
   constexpr bool PF = NS == 2;
   StageBonds<R, W, 0, T> bA;
   StageBonds<R, W, 1, T> bB;
-  StageBonds<R, W, 2, T> none;
   if (PF) fetch_bonds<R, W, 0, T>(bA, a.J, m, m.z0 - 1);
 
   double dE = 0.0;
+  // NS = 3: the +x,+y,+z bonds of this thread's tile site as stage A loaded them on the
+  // last three planes (own0: this step's plane, own2: stage C's)
+  R own0[3] = {}, own1[3] = {}, own2[3] = {};
   for (int32_t t = 0; t < STEPS; ++t) {
     const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
     __syncthreads();
     // the phase alone: colour 0 of plane q is final after stage A, its tile goes out
     // from there
     const bool own_a = NS == 2 && q >= m.z0 && q < m.z0 + kPZ;
-    stage<R, W, 0, OR, 1, T, PF>(lds, a.J, a.out, m, q, bA, hc, false, false, true, own_a);
+    if constexpr (NS == 3) {
+#pragma unroll
+      for (int r = 0; r < (StageShape<W, 2>::COUNT + T - 1) / T; ++r) {
+        const int32_t i = (int32_t)threadIdx.x + r * T;
+        if (i < StageShape<W, 2>::COUNT) {
+          const SiteRef ref = site_ref_a3<W>(m, q, i);
+          const Bonds<R> jb = site_bonds<R, 0>(a.J, m, ref);
+          if (r == 0) {
+            own0[0] = jb.px;
+            own0[1] = jb.py;
+            own0[2] = jb.pz;
+          }
+          phase_site<R, W, 0, OR, 1>(lds, a.out, m, q, ref, jb, hc, false, false, true, false);
+        }
+      }
+    } else {
+      stage<R, W, 0, OR, 1, T, PF>(lds, a.J, a.out, m, q, bA, hc, false, false, true, own_a);
+    }
     if (PF && t + 1 < STEPS) fetch_bonds<R, W, 0, T>(bA, a.J, m, q + 1);
     if (PF && t == 1) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
     __syncthreads();
@@ -381,12 +432,26 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
       }
       __syncthreads();
       // colour 0 of plane q - 2 (one of the tile's own planes) after stage C is final
-      if (t >= 4)
-        dE += stage<R, W, 2, MC, kHitGroup, T, false>(lds, a.J, a.out, m, q - 2, none, hm, rn,
-                                                      false, false, true);
+      if (t >= 4) {
+        // the tile site of this thread: its own bonds from stage A two steps ago
+        const SiteRef ref = site_ref<W, 0, 0>(m, q - 2, (int32_t)threadIdx.x);
+        Bonds<R> jb = site_bonds<R, 0>(a.J, m, ref);
+        jb.px = own2[0];
+        jb.py = own2[1];
+        jb.pz = own2[2];
+        dE += phase_site<R, W, 0, MC, kHitGroup>(lds, a.out, m, q - 2, ref, jb, hm, rn, false,
+                                                 false, true);
+      }
       __syncthreads();
       // colour 0 of plane q + 1 replaces plane q - 2, read by stage C above
       if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
+    }
+    if constexpr (NS == 3) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        own2[c] = own1[c];
+        own1[c] = own0[c];
+      }
     }
     // colour 1 of plane q + 2 replaces plane q + 2 - K1 (last read this step)
     if (t < STEPS - 1) {
