@@ -24,9 +24,9 @@
 // last stage (colour 1 after stage B; colour 0 after stage A, or stage C when the launch
 // carries the Monte Carlo pass).  Stage C runs on the tile only: the
 // expensive Monte Carlo update is never recomputed, and the phase's spin traffic (the
-// planes in LDS) serves the Monte Carlo pass too, as do the +x,+y,+z couplings stage A
-// loads for the tile's sites: stage A takes those sites first, each thread the one it
-// will update in stage C two steps later, and keeps their three couplings.
+// planes in LDS) serves the Monte Carlo pass too, as do the couplings stage A loads for
+// the tile's sites: stage A takes those sites first, each thread the one it will update
+// in stage C two steps later, and keeps their six couplings.
 //
 // The site arithmetic (field of eq. 2 in the fixed order of the single-pass kernel, then
 // the reflection of §4 or the k Metropolis hits / heat-bath draws) is the single pass's,
@@ -373,17 +373,17 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   // The phase alone loads the couplings of its stages' sites a step ahead (the loads
   // stay in flight across the barriers).  With stage C each site's are loaded just
   // before its update (holding them across stage C would cost the registers of the
-  // second workgroup per compute unit, which measures slower) -- except the three a
-  // tile site's stage C takes from stage A, which loaded them two steps earlier.
+  // second workgroup per compute unit, which measures slower); stage C takes its sites'
+  // from stage A, which loaded them two steps earlier.
   constexpr bool PF = NS == 2;
   StageBonds<R, W, 0, T> bA;
   StageBonds<R, W, 1, T> bB;
   if (PF) fetch_bonds<R, W, 0, T>(bA, a.J, m, m.z0 - 1);
 
   double dE = 0.0;
-  // NS = 3: the +x,+y,+z bonds of this thread's tile site as stage A loaded them on the
+  // NS = 3: the six couplings of this thread's tile site as stage A loaded them on the
   // last three planes (own0: this step's plane, own2: stage C's)
-  R own0[3] = {}, own1[3] = {}, own2[3] = {};
+  Bonds<R> own0{}, own1{}, own2{};
   for (int32_t t = 0; t < STEPS; ++t) {
     const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
     __syncthreads();
@@ -397,11 +397,7 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
         if (i < StageShape<W, 2>::COUNT) {
           const SiteRef ref = site_ref_a3<W>(m, q, i);
           const Bonds<R> jb = site_bonds<R, 0>(a.J, m, ref);
-          if (r == 0) {
-            own0[0] = jb.px;
-            own0[1] = jb.py;
-            own0[2] = jb.pz;
-          }
+          if (r == 0) own0 = jb;
           phase_site<R, W, 0, OR, 1>(lds, a.out, m, q, ref, jb, hc, false, false, true, false);
         }
       }
@@ -435,11 +431,7 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
       if (t >= 4) {
         // the tile site of this thread: its own bonds from stage A two steps ago
         const SiteRef ref = site_ref<W, 0, 0>(m, q - 2, (int32_t)threadIdx.x);
-        Bonds<R> jb = site_bonds<R, 0>(a.J, m, ref);
-        jb.px = own2[0];
-        jb.py = own2[1];
-        jb.pz = own2[2];
-        dE += phase_site<R, W, 0, MC, kHitGroup>(lds, a.out, m, q - 2, ref, jb, hm, rn, false,
+        dE += phase_site<R, W, 0, MC, kHitGroup>(lds, a.out, m, q - 2, ref, own2, hm, rn, false,
                                                  false, true);
       }
       __syncthreads();
@@ -447,11 +439,8 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
       if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
     }
     if constexpr (NS == 3) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        own2[c] = own1[c];
-        own1[c] = own0[c];
-      }
+      own2 = own1;
+      own1 = own0;
     }
     // colour 1 of plane q + 2 replaces plane q + 2 - K1 (last read this step)
     if (t < STEPS - 1) {
