@@ -387,6 +387,11 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   for (int32_t t = 0; t < STEPS; ++t) {
     const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
     __syncthreads();
+    // NS = 3: waves in the stages that load couplings and spins (A, B, the plane fetches)
+    // issue ahead of waves in the Metropolis stage, so that while the two workgroups on a
+    // compute unit are in different stages one's loads go out ahead of the other's
+    // arithmetic (a priority that stays the same throughout measures no change).
+    if constexpr (NS == 3) __builtin_amdgcn_s_setprio(2);
     // the phase alone: colour 0 of plane q is final after stage A, its tile goes out
     // from there
     const bool own_a = NS == 2 && q >= m.z0 && q < m.z0 + kPZ;
@@ -427,6 +432,7 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
                                         own);
       }
       __syncthreads();
+      __builtin_amdgcn_s_setprio(0);
       // colour 0 of plane q - 2 (one of the tile's own planes) after stage C is final
       if (t >= 4) {
         // the tile site of this thread: its own bonds from stage A two steps ago
@@ -434,6 +440,7 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
         dE += phase_site<R, W, 0, MC, kHitGroup>(lds, a.out, m, q - 2, ref, own2, hm, rn, false,
                                                  false, true);
       }
+      __builtin_amdgcn_s_setprio(2);
       __syncthreads();
       // colour 0 of plane q + 1 replaces plane q - 2, read by stage C above
       if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
