@@ -388,9 +388,10 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
     const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
     __syncthreads();
     // NS = 3: waves in the stages that load couplings and spins (A, B, the plane fetches)
-    // issue ahead of waves in the Metropolis stage, so that while the two workgroups on a
-    // compute unit are in different stages one's loads go out ahead of the other's
-    // arithmetic (a priority that stays the same throughout measures no change).
+    // take a higher priority than waves in the Metropolis stage.  While the two
+    // workgroups on a compute unit are in different stages, one of them then issues
+    // first instead of both sharing the issue slots: 2-4% per launch, about the same
+    // with the order reversed, none with one priority throughout.
     if constexpr (NS == 3) __builtin_amdgcn_s_setprio(2);
     // the phase alone: colour 0 of plane q is final after stage A, its tile goes out
     // from there
