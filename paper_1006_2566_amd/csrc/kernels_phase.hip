@@ -371,10 +371,10 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   SliceRegs<R, W> r0, r1;
   prologue<R, W, NS>(lds, r0, r1, so, a.in, m);
   // The phase alone loads the couplings of its stages' sites a step ahead (the loads
-  // stay in flight across the barriers).  With stage C each site's are loaded just
-  // before its update (holding them across stage C would cost the registers of the
-  // second workgroup per compute unit, which measures slower); stage C takes its sites'
-  // from stage A, which loaded them two steps earlier.
+  // stay in flight across the barriers).  With stage C, stages A and B load each site's
+  // just before its update (holding them across stage C would cost the registers of the
+  // second workgroup per compute unit, which measures slower), and stage C takes its
+  // sites' from stage A, which loaded them two steps earlier.
   constexpr bool PF = NS == 2;
   StageBonds<R, W, 0, T> bA;
   StageBonds<R, W, 1, T> bB;
