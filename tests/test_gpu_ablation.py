@@ -48,6 +48,10 @@ def run(m, L, dtype, flags, *, k, n_or, R, n, hb=False, T=0.4):
     (64, torch.float32, 4, 2, 1, 4, False),
     (128, torch.float64, 2, 1, 3, 4, False),
     (256, torch.float32, 4, 1, 2, 5, False),
+    # two over-relaxation phases per sweep at L = 256: the first launched alone, the
+    # second carrying the next sweep's colour-0 pass (Metropolis k = 8, heat bath k = 4)
+    (256, torch.float32, 8, 2, 3, 3, False),
+    (256, torch.float32, 4, 2, 3, 3, True),
 ])
 def test_variants_equal_default_schedule(hsg, L, dtype, k, n_or, R, n, hb):
     ref_s, ref_E = run(hsg, L, dtype, 0, k=k, n_or=n_or, R=R, n=n, hb=hb)
