@@ -387,12 +387,12 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   for (int32_t t = 0; t < STEPS; ++t) {
     const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
     __syncthreads();
-    // NS = 3: waves in the stages that load couplings and spins (A, B, the plane fetches)
-    // take a higher priority than waves in the Metropolis stage.  While the two
-    // workgroups on a compute unit are in different stages, one of them then issues
-    // first instead of both sharing the issue slots: 2-4% per launch, about the same
-    // with the order reversed, none with one priority throughout.
-    if constexpr (NS == 3) __builtin_amdgcn_s_setprio(2);
+    // NS = 3: waves take a priority by stage -- 3 in stage A and the plane fetches, 2 in
+    // stage B, 0 in the Metropolis stage.  While the two workgroups on a compute unit are
+    // in different stages, one of them then issues first instead of both sharing the
+    // issue slots: 2-4% per launch (about the same with the order reversed, none with one
+    // priority throughout); B below A adds 1-2% at k = 1.
+    if constexpr (NS == 3) __builtin_amdgcn_s_setprio(3);
     // the phase alone: colour 0 of plane q is final after stage A, its tile goes out
     // from there
     const bool own_a = NS == 2 && q >= m.z0 && q < m.z0 + kPZ;
@@ -426,6 +426,7 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
       // colour 0 of plane q + 1 replaces plane q - 2 (last read by stage B)
       if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
     } else {
+      __builtin_amdgcn_s_setprio(2);
       if (t >= 2) {
         // colour 1 of plane q - 1 is final after stage B: its tile goes out from there
         const bool own = q - 1 >= m.z0 && q - 1 < m.z0 + kPZ;
@@ -441,7 +442,7 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
         dE += phase_site<R, W, 0, MC, kHitGroup>(lds, a.out, m, q - 2, ref, own2, hm, rn, false,
                                                  false, true);
       }
-      __builtin_amdgcn_s_setprio(2);
+      __builtin_amdgcn_s_setprio(3);
       __syncthreads();
       // colour 0 of plane q + 1 replaces plane q - 2, read by stage C above
       if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
