@@ -84,7 +84,8 @@ extern "C" {
 #define HSG_PHASE_LAUNCH 128 /* each over-relaxation phase -- its colour-0 and colour-1
                                passes -- runs as one launch that marches through z with a
                                window of planes in LDS, reading and writing the spins once
-                               (L a multiple of 64, L >= 64; else ignored).  Uses the second
+                               (L a multiple of 64, 64 <= L <= 1024; else ignored: the
+                               launch indexes with 32-bit offsets up to 3 L^3).  Uses the second
                                spin array of the work buffer.  Not with HSG_FUSED */
 #define HSG_PHASE_MC 256   /* as HSG_PHASE_LAUNCH, and when a sweep of the call is followed
                                by another (k_hits > 0), the launch of its last

@@ -33,6 +33,7 @@ HSG_STREAM_LOADS = 64
 HSG_PHASE_LAUNCH = 128
 HSG_PHASE_MC = 256
 FUSED_MIN_L, FUSED_MAX_L = 256, 1024
+PHASE_MIN_L, PHASE_MAX_L = 64, 1024
 FOURIER_VALUES = 65
 L_MAX = 1290
 
@@ -43,8 +44,9 @@ def fused_supported(L: int) -> bool:
 
 
 def phase_supported(L: int) -> bool:
-    """Whether HSG_PHASE_LAUNCH takes effect for an L^3 lattice (L a multiple of 64)."""
-    return L >= 64 and L % 64 == 0
+    """Whether HSG_PHASE_LAUNCH takes effect for an L^3 lattice (L a multiple of 64 with
+    64 <= L <= 1024: the launch's 32-bit element offsets reach 3 L^3)."""
+    return PHASE_MIN_L <= L <= PHASE_MAX_L and L % 64 == 0
 
 
 def default_flags(L: int, dtype=None) -> int:

@@ -117,6 +117,9 @@ constexpr int kPhaseThreads = 512;
 constexpr int kPTY = 16;  // tile rows
 constexpr int kPZ = 32;   // planes per workgroup
 constexpr int kPhaseMinL = 64;
+// Element offsets of the phase launch reach 3 N (six planes of N/2 from one base) and are
+// 32-bit: L = 1024 keeps them below 2^32.
+constexpr int kPhaseMaxL = 1024;
 
 template <typename R>
 struct PhaseArgs {

@@ -477,7 +477,8 @@ hipError_t launch_ns(const PhaseArgs<R>& a, hipStream_t st) {
 }  // namespace
 
 bool phase_supported(int32_t L) {
-  return L >= kPhaseMinL && L % (2 * kPTX) == 0 && L % kPTY == 0 && L % kPZ == 0;
+  return L >= kPhaseMinL && L <= kPhaseMaxL && L % (2 * kPTX) == 0 && L % kPTY == 0 &&
+         L % kPZ == 0;
 }
 
 int32_t phase_blocks(int32_t L) { return (L / 2 / kPTX) * (L / kPTY) * (L / kPZ); }

@@ -121,6 +121,20 @@ def test_phase_launch_needs_the_larger_work_buffer(hsg):
     assert hsg.phase_supported(64) and not hsg.phase_supported(96)
 
 
+def test_phase_launch_capped_where_offsets_fit_32_bits(hsg):
+    """The phase launch indexes six planes of N/2 from one base with 32-bit offsets
+    (up to 3 L^3): it applies up to L = 1024 and is ignored above, which shows in the
+    work size (the second spin array is asked for only where a march applies)."""
+    assert hsg.phase_supported(1024) and not hsg.phase_supported(1088)
+    assert not hsg.phase_supported(1152) and not hsg.phase_supported(1280)
+    for L in (1024, 1152, 1280):
+        assert 3 * L ** 3 < 2 ** 32 or not hsg.phase_supported(L)
+    spin_b, _, work_1024 = hsg.lattice_bytes(1024, torch.float32)
+    assert work_1024 >= spin_b  # second spin array for the phase / fused launches
+    spin_b, _, work_1152 = hsg.lattice_bytes(1152, torch.float32)
+    assert work_1152 < spin_b // 100  # partials only: no march applies at L = 1152
+
+
 def test_sweep_counter_overflow_rejected(hsg):
     lib = hsg.lib()
     d = _desc(hsg, sweep=2 ** 32 - 1)

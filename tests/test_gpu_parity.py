@@ -235,11 +235,15 @@ def test_config1_trajectory_matches_golden(hsg):
 
 @pytest.mark.parametrize("dtype", [F32, F64])
 def test_multi_sweep_trajectory(hsg, dtype):
+    """20 sweeps at L = 16.  Tainted-site cap derived from the flag rate: the same run
+    with the band widened to 1e-3 flags 588 decisions, so about 0.6 are expected within
+    1e-6 (a flag in an early sweep would taint much of this small lattice); the seeded
+    run flags none, and the cap is 1% of the sites."""
     L, seed = 16, 77
     s, J = inputs.random_state(L, 3, dtype)
     got, E_gpu, _ = gpu_run(hsg, L, seed, s, J, T=0.6, k=4, n_or=1, R=10, n_sweeps=20)
     ref, r, taint = oracle_run(L, seed, s, J, T=0.6, k=4, n_or=1, R=10, n_sweeps=20)
-    compare(got, ref, taint, dtype, f"L=16 20 sweeps flagged={r['n_flagged']}", 0.5)
+    compare(got, ref, taint, dtype, f"L=16 20 sweeps flagged={r['n_flagged']}", 0.01)
     if not taint.any():
         assert abs(E_gpu - r["E"]) <= TOL[dtype] * abs(r["E"])
 
