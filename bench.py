@@ -25,52 +25,6 @@ sys.path.insert(0, ROOT)
 METRIC = "spin updates/ns at L=256 FP32 (k=1,4,8) + %HBM roofline; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BYTES_PER_SITE_PHASE = 36.0  # binary32: read spin (12) + 3 bonds (12), write spin (12)
-# 32-bit vector ALU peak of MI355X: the 157.3 TFLOP/s binary32 vector figure counts a
-# fused multiply-add as 2 flops, so 78.6e12 lane operations per second (256 compute
-# units x 128 lanes x 2.4 GHz).
-ALU_PEAK_TOPS = 157.3 / 2
-# Algorithmic 32-bit lane operations of the Metropolis pass (a fused multiply-add, a
-# compare, a select, each half of a 32x32->64 product counts one):
-#   per site:  local field 3 x (1 mul + 5 fma) = 18, sigma.h 3         -> 21
-#   per Philox4x32-10 block: 10 rounds x (2 products x 2 halves + 4 xor) = 80;
-#              a hit takes three of a block's four words, so k hits draw
-#              ceil(3k / 4) blocks
-#   per hit:   three uniforms 3 x (shift, or, convert, scale)           = 12
-#              trial point: 2u-1, 1-z^2, sqrt, 4u, rint, r, r^2, sin (5), cos (5),
-#              quadrant (convert, and, 4 selects), rho cos, rho sin     = 25
-#              decision: s.h (3), dE, -beta dE, exp (2), dE <= 0, u < p, or,
-#              4 selects (spin, s.h), energy sum (convert, add)         = 16
-OPS_PER_SITE = 21
-OPS_PER_BLOCK = 80
-OPS_PER_HIT = 12 + 25 + 16
-# over-relaxation of a site: local field and sigma.h (21), h.h (3), 2 sigma.h / h.h (2),
-# h.h > 0 (1), reflection 3 x (fma, select) (6)
-OPS_PER_SITE_OR = 21 + 3 + 2 + 1 + 6
-
-
-def ops_per_site_pass(k: int) -> int:
-    """Algorithmic lane operations of one site's Metropolis update with k hits."""
-    return OPS_PER_SITE + OPS_PER_HIT * k + OPS_PER_BLOCK * ((3 * k + 3) // 4)
-
-
-# Heat-bath draw (exact sample of exp(beta sigma.h) on the sphere), each library
-# function (expm1, log1p or log, square root, division) counted as one operation:
-#   two uniforms 2 x (shift-in, subtract)                                = 4
-#   |h|: h.h (3), root, a = beta |h|, a > 0                              = 6
-#   cosine to the field: 1 - u0, -2a, expm1, w q (2), w q <= 1/2,
-#     log1p or log (3), divide, add, two clamps (4)                      = 15
-#   rho = sqrt(1 - c^2) (2), azimuth as the Metropolis trial point (20) = 22
-#   frame about h/|h|: h.h > 0, three divisions, sign (2), -1/(sgn + n_z)
-#     (2), b (2), e1 (6), e2 (3)                                         = 19
-#   point: rho cos, rho sin, three components x (mul, fma, fma)          = 11
-#   energy change and sum: trial.h (3), dE, convert, add                = 6
-# A draw takes two of a block's four words: k draws draw ceil(k / 2) blocks.
-OPS_PER_DRAW = 4 + 6 + 15 + 22 + 19 + 11 + 6
-
-
-def ops_per_site_heat_bath(k: int) -> int:
-    """Algorithmic lane operations of one site's heat-bath update with k draws."""
-    return OPS_PER_SITE + OPS_PER_DRAW * k + OPS_PER_BLOCK * ((k + 1) // 2)
 _COMMON_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/csrc/hsg_device.h",
                    "paper_1006_2566_amd/csrc/hsg_internal.h")
 # The kernels that can dominate the headline sweep: the binary32 Metropolis colour pass,
@@ -92,9 +46,25 @@ DOMINANT = {
         "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_phase.hip",),
         "traffic_file": "profiles/traffic_phase_mc_L256_f32.txt",
         "title": "one over-relaxation phase with the next colour-0 Metropolis pass",
-        "sites": 1.0,  # the phase's compulsory traffic: every site read and written once
+        # an over-relaxation phase (every site once) and half a Metropolis phase (the
+        # colour-0 sites): 1.5 site-phases per site
+        "sites": 1.5,
+    },
+    "phase": {
+        "kernel": "phase_kernel<float, 2, OverRelax>",
+        "trace_name": "phase_kernel<float, 2, (hsg::PassMode)1>",
+        "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_phase.hip",),
+        "traffic_file": "profiles/traffic_phase_L256_f32.txt",
+        "title": "one over-relaxation phase",
+        "sites": 1.0,
     },
 }
+# launch kinds of hsg_sweep_timed -> (dominant-kernel entry, site-phases per launch in
+# units of N): a colour pass updates half the sites (half a phase)
+LAUNCH_ROOFLINE = {1: ("metropolis_pass", 0.5), 2: (None, 0.5), 3: ("phase", 1.0),
+                   4: ("phase_mc", 1.5)}
+CLOCK_GHZ = 2.4  # MI355X peak engine clock
+N_CU = 256
 
 
 def parse():
@@ -130,16 +100,20 @@ def parse():
                     help="skip timing the headline sweep with binary64 spins")
     ap.add_argument("--no-heat-bath", action="store_true",
                     help="skip timing the headline sweep with heat-bath draws")
+    ap.add_argument("--no-large-L", dest="large_L", action="store_false",
+                    help="skip the L = 512 row")
     ap.add_argument("--no-observables", action="store_true",
                     help="skip timing the Fourier-overlap records (chi_SG, xi inputs)")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
                          "(calibrates FETCH_SIZE / WRITE_SIZE), then 3 sweeps of the headline "
                          "configuration; prints no JSON")
-    ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="turn the counter_collection.csv files of a FETCH_SIZE and a "
-                         "WRITE_SIZE run of --counters into the per-launch traffic summaries "
-                         "of the kernels the run dispatched ("
+    ap.add_argument("--reduce-counters", nargs="+", metavar="CSV",
+                    help="FETCH_CSV WRITE_CSV [ISSUE_CSV [TRACE_CSV]]: turn the "
+                         "counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE run of "
+                         "--counters (and optionally of an SQ_INSTS_VALU + GRBM_GUI_ACTIVE run "
+                         "and the kernel_trace.csv of a --kernel-trace run of the same command) "
+                         "into the per-launch summaries of the kernels the run dispatched ("
                          + ", ".join(d["traffic_file"] for d in DOMINANT.values()) + "), then exit")
     return ap.parse_args()
 
@@ -154,27 +128,54 @@ def source_hash(name: str) -> str:
     return h.hexdigest()[:16]
 
 
-def read_counter_csv(path):
-    """{kernel name: [value per dispatch]} of one counter from rocprofv3's CSV."""
+def read_counter_csv(path, counter=None):
+    """{kernel name: [value per dispatch]} of one counter from rocprofv3's CSV (the only
+    counter of the file, or the one named)."""
     import csv
     out = {}
     with open(path, newline="") as f:
         for row in csv.DictReader(f):
+            if counter is not None and row.get("Counter_Name") != counter:
+                continue
             out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
     return out
 
 
-def reduce_counters(fetch_csv, write_csv):
+def read_trace_csv(path):
+    """{kernel name: [duration in us per dispatch]} from rocprofv3's kernel_trace.csv."""
+    import csv
+    out = {}
+    with open(path, newline="") as f:
+        for row in csv.DictReader(f):
+            d = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3
+            out.setdefault(row["Kernel_Name"], []).append(d)
+    return out
+
+
+# vector instruction classes counted beside SQ_INSTS_VALU for the issue mix
+VALU_MIX = ("SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64", "SQ_INSTS_VALU_FMA_F32",
+            "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_TRANS_F32")
+
+
+def reduce_counters(fetch_csv, write_csv, issue_csv=None, trace_csv=None):
     """FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of each dominant-kernel candidate the
     run dispatched, each scaled by what the same counter reads for the 1 GiB device copy
-    of the --counters run."""
+    of the --counters run; with issue_csv, its vector wave-instructions per launch and per
+    compute unit and cycle (SQ_INSTS_VALU / (256 x GRBM_GUI_ACTIVE / 8 XCDs)); with
+    trace_csv, its mean kernel-trace duration."""
     fetch, write = read_counter_csv(fetch_csv), read_counter_csv(write_csv)
+    issue = {c: read_counter_csv(issue_csv, c) for c in ("SQ_INSTS_VALU", "GRBM_GUI_ACTIVE")
+             + VALU_MIX} if issue_csv else {}
+    trace = read_trace_csv(trace_csv) if trace_csv else {}
 
     def pick(d, key):
         names = [n for n in d if key(n)]
         if len(names) > 1:
             raise SystemExit(f"expected one kernel, found {names}")
         return d[names[0]] if names else None
+
+    def mean(v):
+        return sum(v) / len(v)
 
     copy_f = pick(fetch, lambda n: "copy" in n.lower())
     copy_w = pick(write, lambda n: "copy" in n.lower())
@@ -185,25 +186,45 @@ def reduce_counters(fetch_csv, write_csv):
     w_scale = gib_kib / max(copy_w)
     written = 0
     for name, d in DOMINANT.items():
-        k_f = pick(fetch, lambda n: d["trace_name"] in n)
-        k_w = pick(write, lambda n: d["trace_name"] in n)
+        match = lambda n, d=d: d["trace_name"] in n  # noqa: E731
+        k_f = pick(fetch, match)
+        k_w = pick(write, match)
         if k_f is None or k_w is None:
             continue
-        f_b = sum(k_f) / len(k_f) * 1024 * f_scale
-        w_b = sum(k_w) / len(k_w) * 1024 * w_scale
+        f_b = mean(k_f) * 1024 * f_scale
+        w_b = mean(k_w) * 1024 * w_scale
         lines = [
             f"# HBM traffic of {d['title']} ({d['kernel']}), L=256 binary32, k=4",
             "# commands: rocprofv3 --pmc FETCH_SIZE -d <dir> -o run --output-format csv -- "
-            "python bench.py --counters   (then the same with WRITE_SIZE)",
-            "#           python bench.py --reduce-counters <fetch csv> <write csv>",
+            "python bench.py --counters   (then the same with WRITE_SIZE, and with "
+            "SQ_INSTS_VALU GRBM_GUI_ACTIVE + the SQ_INSTS_VALU_* classes; and "
+            "rocprofv3 --kernel-trace --output-format csv)",
+            "#           python bench.py --reduce-counters <fetch csv> <write csv> [<issue csv> "
+            "[<kernel_trace csv>]]",
             f"copy_fetch_kib={max(copy_f):.0f} fetch_scale={f_scale:.4f}",
             f"copy_write_kib={max(copy_w):.0f} write_scale={w_scale:.4f}",
             f"dispatches={len(k_f)}",
             f"fetch_bytes_per_launch={f_b:.0f}",
             f"write_bytes_per_launch={w_b:.0f}",
             f"algorithmic_bytes_per_launch={(1 << 24) * d['sites'] * BYTES_PER_SITE_PHASE:.0f}",
-            f"source_hash={source_hash(name)}",
         ]
+        v = pick(issue.get("SQ_INSTS_VALU", {}), match)
+        g = pick(issue.get("GRBM_GUI_ACTIVE", {}), match)
+        if v:
+            lines.append(f"valu_insts_per_launch={mean(v):.0f}")
+            if g:
+                lines.append(f"valu_insts_per_cu_cycle={mean(v) / (N_CU * mean(g) / 8):.3f}")
+            mix = []
+            for c in VALU_MIX:
+                x = pick(issue.get(c, {}), match)
+                if x:
+                    mix.append(f"{c[len('SQ_INSTS_VALU_'):].lower()}:{mean(x) / mean(v):.3f}")
+            if mix:
+                lines.append("valu_mix=" + ",".join(mix))
+        t = pick(trace, match)
+        if t:
+            lines.append(f"trace_dispatches={len(t)} trace_mean_us={mean(t):.2f}")
+        lines.append(f"source_hash={source_hash(name)}")
         with open(os.path.join(ROOT, d["traffic_file"]), "w") as f:
             f.write("\n".join(lines) + "\n")
         print("\n".join(lines))
@@ -212,10 +233,9 @@ def reduce_counters(fetch_csv, write_csv):
         raise SystemExit("none of the dominant-kernel candidates was dispatched")
 
 
-def measured_traffic(name: str):
-    """Copy-calibrated HBM bytes per launch of a dominant-kernel candidate from its
-    committed counter summary, or None when its sources changed since the counters were
-    taken."""
+def counter_summary(name: str) -> dict | None:
+    """key=value pairs of a dominant-kernel candidate's committed counter summary, or None
+    when it is missing or its sources changed since the counters were taken."""
     path = os.path.join(ROOT, DOMINANT[name]["traffic_file"])
     if not os.path.exists(path):
         return None
@@ -226,9 +246,7 @@ def measured_traffic(name: str):
                 for item in line.split():
                     k, _, v = item.partition("=")
                     kv[k] = v
-    if kv.get("source_hash") != source_hash(name):
-        return None
-    return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+    return kv if kv.get("source_hash") == source_hash(name) else None
 
 
 def note(msg: str) -> None:
@@ -265,24 +283,27 @@ def binary64_leg(hsg, args, torch, flags):
             "spin_updates_per_ns": L ** 3 * (args.k + args.n_or) / (ms * 1e6)}
 
 
-def heat_bath_leg(hsg, lat, torch, args, flags, pass_flags):
-    """The headline sweep with k heat-bath draws per site in place of the Metropolis
-    hits (same traversal), and the heat-bath colour pass alone against the vector-ALU
-    roofline (Metropolis-free sweeps, two passes each, events on the launch stream)."""
+def heat_bath_leg(hsg, lat, torch, args, flags):
+    """The headline sweep with a heat-bath draw in place of the Metropolis hits (same
+    traversal).  A heat-bath draw does not depend on the spin it replaces, so a site
+    takes one draw per Monte Carlo phase (k draws would leave the last): one update per
+    site and phase.  The heat-bath colour pass is timed from the launches of the sweep
+    (hsg_sweep_timed)."""
     N = lat.L ** 3
     steps = max(10, args.steps // 2)
-    ms = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=args.renorm_every,
-                     steps=steps, warmup=2, flags=flags | hsg.HSG_HEAT_BATH)
-    ms_pass = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=steps, warmup=2,
-                          flags=pass_flags | hsg.HSG_HEAT_BATH) / 2.0
-    ops = N / 2 * ops_per_site_heat_bath(args.k)
-    tops = ops / (ms_pass * 1e-3) / 1e12
-    return {"k_draws": args.k, "steps": steps, "ms_per_step": ms, "flags": flags | hsg.HSG_HEAT_BATH,
-            "spin_updates_per_ns": N * (args.k + args.n_or) / (ms * 1e6),
-            "pass": {"kernel": "colour_pass_kernel<float, HeatBath>", "bound": "alu",
-                     "kernel_ms": ms_pass, "ops_per_launch": ops, "achieved": tops,
-                     "peak": ALU_PEAK_TOPS, "unit": "TOP/s", "frac": tops / ALU_PEAK_TOPS,
-                     "draws_per_ns": N / 2 * args.k / (ms_pass * 1e6)}}
+    f = flags | hsg.HSG_HEAT_BATH
+    ms = time_sweeps(lat, torch, T=args.T, k=1, n_or=args.n_or, R=args.renorm_every,
+                     steps=steps, warmup=2, flags=f)
+    launches = traced_launches(hsg, lat, T=args.T, k=1, n_or=args.n_or, R=args.renorm_every,
+                               n=steps, flags=f)
+    out = {"draws_per_site_phase": 1, "steps": steps, "ms_per_step": ms, "flags": f,
+           "spin_updates_per_ns": N * (1 + args.n_or) / (ms * 1e6),
+           "launches": {hsg.LAUNCH_NAMES[kd]: v for kd, v in launches.items()}}
+    if hsg.LAUNCH_MC_PASS in launches:
+        ms_pass = launches[hsg.LAUNCH_MC_PASS]["mean_ms"]
+        out["pass"] = {"kernel": "colour_pass_kernel<float, HeatBath>", "kernel_ms": ms_pass,
+                       "draws_per_ns": N / 2 / (ms_pass * 1e6)}
+    return out
 
 
 def observables_leg(hsg, lat, torch, steps):
@@ -423,32 +444,177 @@ def served_leg(args, torch):
                           for k, v in srv.stats.items()}}
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(args):
-    """The CPU oracle, unchanged, on the host cores: the same L, k, n_or and T,
-    as many whole sweeps as fit in about args.cpu_seconds (at least one)."""
+    """The CPU oracle, unchanged, on the host cores: the same L, k, n_or and T, as many
+    whole sweeps as fit in about args.cpu_seconds (at least one) with every OpenMP
+    thread, then one sweep on a single thread; and the paper's own workload (§4,
+    Table 2: over-relaxation only, L = 128, binary32, 100 sweeps) on all threads and,
+    for 10 sweeps, on one."""
     import numpy as np
 
     import oracle as O
 
     L = args.L
+    threads = O.threads()
     spins, J = O.init(L, 1, np.float32)
     E = O.energy(L, spins, J)
-    n = 0
+
+    def run(n_max, seconds, sweep0=0, **kw):
+        nonlocal E
+        n, t0 = 0, time.perf_counter()
+        while n < n_max:
+            E = O.sweep(L, 1, spins, J, n_sweeps=1, sweep0=sweep0 + n, E=E, **kw)["E"]
+            n += 1
+            if time.perf_counter() - t0 >= seconds:
+                break
+        return n, time.perf_counter() - t0
+
+    kw = dict(T=args.T, k=args.k, n_or=args.n_or, renorm_every=args.renorm_every)
+    n, dt = run(1 << 30, args.cpu_seconds, **kw)
+    per = L ** 3 * (args.k + args.n_or)
+    O.set_threads(1)
+    try:
+        n1, dt1 = run(1, 0.0, sweep0=n, **kw)
+        s128, J128 = O.init(128, 1, np.float32)
+        t0 = time.perf_counter()
+        O.sweep(128, 1, s128, J128, T=1.0, k=0, n_or=1, n_sweeps=10)
+        or1 = 128 ** 3 * 10 / ((time.perf_counter() - t0) * 1e9)
+    finally:
+        O.set_threads(threads)
     t0 = time.perf_counter()
-    while True:
-        r = O.sweep(L, 1, spins, J, T=args.T, k=args.k, n_or=args.n_or,
-                    renorm_every=args.renorm_every, n_sweeps=1, sweep0=n, E=E)
-        E = r["E"]
-        n += 1
-        if time.perf_counter() - t0 >= args.cpu_seconds:
-            break
-    dt = time.perf_counter() - t0
-    updates = L ** 3 * (args.k + args.n_or) * n
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": updates / (dt * 1e9), "unit": "spin updates/ns", "cores": cores,
+    O.sweep(128, 1, s128, J128, T=1.0, k=0, n_or=1, n_sweeps=100)
+    orN = 128 ** 3 * 100 / ((time.perf_counter() - t0) * 1e9)
+    return {"value": per * n / (dt * 1e9), "unit": "spin updates/ns", "cores": threads,
             "kind": "oracle",
             "sample": f"L={L} binary32, {n} sweep(s) of k={args.k} Metropolis + {args.n_or} "
-                      f"over-relaxation, T={args.T}, {dt:.1f} s wall"}
+                      f"over-relaxation, T={args.T}, {dt:.1f} s wall on {threads} OpenMP "
+                      f"threads",
+            "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+            "single_thread": {"value": per * n1 / (dt1 * 1e9), "unit": "spin updates/ns",
+                              "sample": f"{n1} sweep, {dt1:.1f} s"},
+            "paper_workload": {
+                "workload": "over-relaxation only, L=128, binary32 (the paper's Table 2 "
+                            "benchmark)",
+                "all_threads": {"updates_per_ns": orN, "ns_per_update": 1.0 / orN,
+                                "threads": threads, "sweeps": 100},
+                "single_thread": {"updates_per_ns": or1, "ns_per_update": 1.0 / or1,
+                                  "sweeps": 10},
+                "paper_i7_ns_per_update": {"1_thread_sse": 13.5, "8_threads_sse": 5.0}}}
+
+
+def traced_launches(hsg, lat, *, T, k, n_or, R, n, flags) -> dict:
+    """{launch kind: count, mean and total ms} over n sweeps through hsg_sweep_timed."""
+    lat.sweep(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=2, flags=flags)
+    rec = lat.sweep_timed(T=T, k=k, n_or=n_or, renorm_every=R, n_sweeps=n, flags=flags,
+                          capacity=16 * n + 16)
+    out = {}
+    for kd, ms in rec:
+        d = out.setdefault(kd, {"count": 0, "total_ms": 0.0})
+        d["count"] += 1
+        d["total_ms"] += ms
+    for d in out.values():
+        d["mean_ms"] = d["total_ms"] / d["count"]
+    return out
+
+
+def kernel_roofline(kind: int, stats: dict, N: int, counted: bool, brief: bool = False) -> dict:
+    """HBM roofline of one kind of launch: algorithmic bytes per launch (36 B per site-phase
+    x the site-phases one launch performs) over its event-timed mean duration."""
+    name, site_phases = LAUNCH_ROOFLINE[kind]
+    nbytes = site_phases * N * BYTES_PER_SITE_PHASE
+    ms = stats["mean_ms"]
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": gbs / HBM_PEAK_GBS, "kernel_ms": ms, "bytes_per_launch": nbytes,
+           "site_phases_per_launch": site_phases * N, "launches": stats["count"]}
+    if name:
+        out["kernel"] = DOMINANT[name]["kernel"]
+    if brief:
+        return out
+    kv = counter_summary(name) if (name and counted) else None
+    out["traffic"] = (float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+                      if kv else None)
+    if kv and "valu_insts_per_launch" in kv:
+        insts = float(kv["valu_insts_per_launch"])
+        floor_ms = insts / (N_CU * CLOCK_GHZ * 1e9) * 1e3  # one wave-instruction/CU/cycle
+        out["vector_issue"] = {
+            "valu_wave_insts_per_launch": insts,
+            "floor_ms_at_2.4GHz": floor_ms,
+            "issue_frac": floor_ms / ms,
+            "profiled_insts_per_cu_cycle": float(kv.get("valu_insts_per_cu_cycle", "nan")),
+            "mix": kv.get("valu_mix", "")}
+    if kv and "trace_mean_us" in kv:
+        out["kernel_ms_rocprofv3"] = float(kv["trace_mean_us"]) * 1e-3
+    return out
+
+
+def copy_bandwidth(torch) -> float:
+    """GB/s of a 1 GiB device-to-device copy (read + write), events on the stream."""
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    stream = torch.cuda.current_stream()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(10):
+        b.copy_(a)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / 10
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * (1 << 30) / (ms * 1e-3) / 1e9
+
+
+def fit_multi_hit(ms_by_k: dict, ms0: float, N: int) -> dict:
+    """The paper's multi-hit law: per-hit time t(k) = t_inf + c / k, where c is the
+    memory (load and store) cost of a site's Monte Carlo update and t_inf the cost of a
+    hit.  t(k) is the Monte Carlo phase's time per hit, (sweep(k) - sweep(0)) / (N k)."""
+    import numpy as np
+    ks = sorted(k for k in ms_by_k if k > 0)
+    t = np.array([(ms_by_k[k] - ms0) * 1e9 / (N * k) for k in ks])  # ps per hit
+    A = np.stack([np.ones(len(ks)), 1.0 / np.array(ks, dtype=float)], axis=1)
+    (t_inf, c), *_ = np.linalg.lstsq(A, t, rcond=None)
+    fit = A @ np.array([t_inf, c])
+    return {"k": ks, "t_ps_per_hit": t.tolist(), "fit_ps": fit.tolist(),
+            "max_rel_residual": float(np.max(np.abs(fit - t) / t)),
+            "t_inf_ps": float(t_inf), "c_ps": float(c),
+            "hits_per_ns_asymptotic": 1e3 / float(t_inf),
+            "ms_per_sweep_k0": ms0,
+            "note": "t(k) = (sweep(k) - sweep(k=0)) / (N k), both with the same over-relaxation"}
+
+
+def large_lattice_leg(hsg, torch, args) -> dict:
+    """The largest lattice of the large-lattice configuration, L = 512 (134M spins),
+    binary32, the headline sweep (k + n_or, T, renormalisation), the library's traversal."""
+    L = 512
+    lat = hsg.Lattice(L, torch.float32, seed=1)
+    flags = hsg.default_flags(L, torch.float32)
+    steps = max(4, args.steps // 5)
+    ms = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=args.renorm_every,
+                     steps=steps, warmup=2, flags=flags)
+    N = L ** 3
+    del lat
+    torch.cuda.empty_cache()
+    return {"L": L, "dtype": "f32", "k": args.k, "n_or": args.n_or, "steps": steps,
+            "flags": flags, "ms_per_step": ms,
+            "spin_updates_per_ns": N * (args.k + args.n_or) / (ms * 1e6),
+            "hbm_frac_36B": N * (1 + args.n_or) * BYTES_PER_SITE_PHASE / (ms * 1e-3) / 1e9 /
+            HBM_PEAK_GBS}
 
 
 def main():
@@ -501,73 +667,33 @@ def main():
                          (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
         note(f"k={k}: {upd:.1f} spin updates/ns (flags {flags})")
 
-    # The Metropolis colour pass (half the sites, k hits each): its average duration from
-    # Metropolis-only sweeps (two passes each, one energy fold per call) timed with events
-    # on the launch stream.  The over-relaxation pass, bound by HBM, is timed the same way.
-    pass_flags = flags & ~(hsg.HSG_FUSED | hsg.HSG_PHASE_LAUNCH | hsg.HSG_PHASE_MC)
-    ms_mh_pass = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=0, R=0, steps=args.steps,
-                             warmup=2, flags=pass_flags) / 2.0
-    ms_or_pass = time_sweeps(lat, torch, T=args.T, k=0, n_or=1, R=0, steps=args.steps,
-                             warmup=2, flags=pass_flags) / 2.0
-    # the over-relaxation phase as one launch (when the traversal uses it): both passes
-    # of the phase, 36 B per site algorithmic
-    or_phase = None
-    phase = bool(flags & (hsg.HSG_PHASE_LAUNCH | hsg.HSG_PHASE_MC)) and hsg.phase_supported(L)
-    if phase:
-        ms_ph = time_sweeps(lat, torch, T=args.T, k=0, n_or=1, R=0, steps=args.steps, warmup=2,
-                            flags=flags)
-        gbs = N * BYTES_PER_SITE_PHASE / (ms_ph * 1e-3) / 1e9
-        or_phase = {"kernel": "phase_kernel<float, 2, OverRelax>", "bound": "hbm",
-                    "kernel_ms": ms_ph, "achieved_GBs": gbs, "frac": gbs / HBM_PEAK_GBS}
-    head = per_k[str(args.k)]
-    sites_pass = N / 2
-    ops_pass = sites_pass * ops_per_site_pass(args.k)
-    achieved = ops_pass / (ms_mh_pass * 1e-3) / 1e12
-    counted = L == 256 and args.k == 4
-    metropolis = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
-                  "frac": achieved / ALU_PEAK_TOPS,
-                  "traffic": measured_traffic("metropolis_pass") if counted else None,
-                  "kernel": DOMINANT["metropolis_pass"]["kernel"], "kernel_ms": ms_mh_pass,
-                  "ops_per_launch": ops_pass,
-                  "hits_per_ns": sites_pass * args.k / (ms_mh_pass * 1e6),
-                  "hbm_frac_36B": sites_pass * BYTES_PER_SITE_PHASE / (ms_mh_pass * 1e-3) /
-                  1e9 / HBM_PEAK_GBS}
-    extras = {"overrelax_pass": {"bound": "hbm", "kernel_ms": ms_or_pass,
-                                 "achieved_GBs": sites_pass * BYTES_PER_SITE_PHASE /
-                                 (ms_or_pass * 1e-3) / 1e9,
-                                 "frac": sites_pass * BYTES_PER_SITE_PHASE /
-                                 (ms_or_pass * 1e-3) / 1e9 / HBM_PEAK_GBS},
-              "overrelax_phase": or_phase}
-    if phase and flags & hsg.HSG_PHASE_MC and args.k > 0 and args.n_or > 0:
-        # Dominant kernel: the over-relaxation phase with the next sweep's colour-0
-        # Metropolis pass.  A call of n sweeps runs n + 1 Metropolis passes, n - 1 such
-        # launches, (n - 1)(n_or - 1) + n_or plain phases and fixed per-call work, so the
-        # growth of the call's time per sweep (two call lengths, events on the launch
-        # stream) less a Metropolis pass and n_or - 1 phases is the launch's duration.
-        n1, n2 = max(4, args.steps // 5), max(args.steps, 2 * max(4, args.steps // 5))
-        tot = [time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=0, steps=n,
-                           warmup=2, flags=flags) * n for n in (n1, n2)]
-        ms_f = (tot[1] - tot[0]) / (n2 - n1) - ms_mh_pass - (args.n_or - 1) * or_phase["kernel_ms"]
-        bytes_f = N * BYTES_PER_SITE_PHASE
-        ops_f = sites_pass * ops_per_site_pass(args.k) + N * OPS_PER_SITE_OR
-        gbs_f = bytes_f / (ms_f * 1e-3) / 1e9
-        tops_f = ops_f / (ms_f * 1e-3) / 1e12
-        # the larger of the two floors binds: the phase's compulsory bytes at HBM peak
-        # against both passes' lane operations at the vector peak
-        hbm_bound = bytes_f / HBM_PEAK_GBS >= ops_f / (ALU_PEAK_TOPS * 1e3)
-        roofline = {"bound": "hbm" if hbm_bound else "alu",
-                    "achieved": gbs_f if hbm_bound else tops_f,
-                    "peak": HBM_PEAK_GBS if hbm_bound else ALU_PEAK_TOPS,
-                    "unit": "GB/s" if hbm_bound else "TOP/s",
-                    "frac": gbs_f / HBM_PEAK_GBS if hbm_bound else tops_f / ALU_PEAK_TOPS,
-                    "traffic": measured_traffic("phase_mc") if counted else None,
-                    "kernel": DOMINANT["phase_mc"]["kernel"], "kernel_ms": ms_f,
-                    "bytes_per_launch": bytes_f, "ops_per_launch": ops_f,
-                    "alu_achieved": tops_f, "alu_frac": tops_f / ALU_PEAK_TOPS,
-                    "metropolis_pass": metropolis, **extras}
-    else:
-        roofline = {**metropolis, **extras}
+    # Every launch of the headline sweep timed with HIP events on the launch stream
+    # (hsg_sweep_timed, the same sweeps): per-kind durations, the dominant kernel's
+    # roofline against its algorithmic bytes (36 B per site-phase).
+    launches = traced_launches(hsg, lat, T=args.T, k=args.k, n_or=args.n_or, R=R,
+                               n=args.steps, flags=flags)
+    dom_kind = max((kd for kd in launches if kd in LAUNCH_ROOFLINE),
+                   key=lambda kd: launches[kd]["total_ms"])
+    roofline = kernel_roofline(dom_kind, launches[dom_kind], N, counted=L == 256 and args.k == 4)
+    roofline["launches"] = {hsg.LAUNCH_NAMES[kd]: v for kd, v in launches.items()}
+    note(f"roofline: {roofline['kernel']} {roofline['kernel_ms'] * 1e3:.1f} us, "
+         f"frac {roofline['frac']:.3f}")
+    copy = copy_bandwidth(torch)
+    roofline["copy_GBs"] = copy
+    roofline["frac_of_copy"] = roofline["achieved"] / copy
+    # the other kinds of launch of the headline sweep against the same roofline
+    roofline["others"] = {hsg.LAUNCH_NAMES[kd]: kernel_roofline(kd, launches[kd], N, counted=False,
+                                                                brief=True)
+                          for kd in launches if kd in LAUNCH_ROOFLINE and kd != dom_kind}
 
+    # the multi-hit law of the paper (§5, Table 3): per-hit time of the Monte Carlo phase,
+    # t(k) = (sweep(k) - sweep(k=0)) / (N k), fitted to t_inf + c / k
+    ms0 = time_sweeps(lat, torch, T=args.T, k=0, n_or=args.n_or, R=R, steps=args.steps,
+                      warmup=2, flags=flags)
+    multi_hit = fit_multi_hit({int(k): v["ms_per_step"] for k, v in per_k.items()}, ms0, N)
+    note(f"multi-hit: t_inf {multi_hit['t_inf_ps']:.2f} ps/hit, c {multi_hit['c_ps']:.2f} ps")
+
+    head = per_k[str(args.k)]
     rec = {"metric": METRIC,
            "value": head["spin_updates_per_ns"], "unit": "spin updates/ns", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
@@ -577,15 +703,16 @@ def main():
                                   f"T={args.T}, sweep = Metropolis k={args.k} + "
                                   f"{args.n_or} over-relaxation, renormalise every {R}",
                       "L": L, "k": args.k, "n_or": args.n_or, "T": args.T, "flags": flags},
-           "per_k": per_k, "roofline": roofline}
-    note(f"roofline: {roofline['kernel']} {roofline['kernel_ms'] * 1e3:.1f} us, "
-         f"frac {roofline['frac']:.3f}")
+           "per_k": per_k, "roofline": roofline, "multi_hit": multi_hit}
+    if args.large_L:
+        rec["large_lattice"] = large_lattice_leg(hsg, torch, args)
+        note("large-lattice leg done")
     if not args.no_binary64:
         rec["binary64"] = binary64_leg(hsg, args, torch, flags if args.flags is not None
                                        else hsg.default_flags(L, torch.float64))
         note("binary64 leg done")
     if not args.no_heat_bath:
-        rec["heat_bath"] = heat_bath_leg(hsg, lat, torch, args, flags, pass_flags)
+        rec["heat_bath"] = heat_bath_leg(hsg, lat, torch, args, flags)
         note("heat-bath leg done")
     if not args.no_observables:
         rec["observables"] = observables_leg(hsg, lat, torch, args.steps)

@@ -151,6 +151,27 @@ int hsg_export(const hsg_lattice *lat, void *canon_spins, void *canon_J, void *s
  * the sweep index would pass 2^32. */
 int hsg_sweep(hsg_lattice *lat, const hsg_sweep_params *p, int32_t n_sweeps, void *stream);
 
+/* Kinds of launch reported by hsg_sweep_timed. */
+#define HSG_LAUNCH_OTHER 0        /* renormalisation, energy fold */
+#define HSG_LAUNCH_MC_PASS 1      /* Metropolis or heat-bath colour pass */
+#define HSG_LAUNCH_OR_PASS 2      /* over-relaxation colour pass */
+#define HSG_LAUNCH_OR_PHASE 3     /* over-relaxation phase in one launch (HSG_PHASE_LAUNCH) */
+#define HSG_LAUNCH_OR_PHASE_MC 4  /* the same carrying the next colour-0 Monte Carlo pass
+                                     (HSG_PHASE_MC) */
+#define HSG_LAUNCH_MARCH 5        /* fused passes (HSG_FUSED) */
+
+/* Measurement form of hsg_sweep: the same sweeps (same arguments, same results), with a
+ * pair of HIP events recorded on `stream` around each of the call's first `capacity`
+ * kernel launches.  Synchronous: returns after the stream has passed the last
+ * recorded launch, with kinds[i] (HSG_LAUNCH_*) and ms[i] (milliseconds between the
+ * two events, the launch's duration in stream order) for launch i < *n_recorded.
+ * kinds and ms are host arrays of capacity entries (NULL when capacity = 0).  The
+ * events are created and destroyed inside the call.  HSG_EINVAL for capacity < 0,
+ * missing outputs or a call nested inside another (per thread); HSG_EDEVICE if an
+ * event cannot be created or read. */
+int hsg_sweep_timed(hsg_lattice *lat, const hsg_sweep_params *p, int32_t n_sweeps, void *stream,
+                    int32_t capacity, int32_t *kinds, float *ms, int32_t *n_recorded);
+
 /* *out_dev = the energy H: the tracked value (recompute = 0) or a fresh binary64
  * sum over all bonds (recompute != 0; deterministic order).  out_dev is device
  * memory for one double. */

@@ -48,12 +48,17 @@ def lib():
         L.hsgo_poly_coefs_f32.argtypes = [_P]
         L.hsgo_pt_swap.argtypes = [_I32, _P, _P, _P, _U64, _U32, _U32, _P]
         L.hsgo_pt_swap.restype = ctypes.c_int
+        L.hsgo_threads.restype = ctypes.c_int
+        L.hsgo_set_threads.argtypes = [ctypes.c_int]
         for suf, real in (("f32", ctypes.c_float), ("f64", ctypes.c_double)):
             getattr(L, f"hsgo_sincos_2pi_{suf}").argtypes = [real, _P, _P]
             getattr(L, f"hsgo_trial_spin_{suf}").argtypes = [real, real, _P]
             getattr(L, f"hsgo_init_{suf}").argtypes = [_I32, _U64, _P, _P]
             getattr(L, f"hsgo_local_field_{suf}").argtypes = [_I32, _P, _P, _I32, _I32, _I32, _P]
             getattr(L, f"hsgo_overrelax_site_{suf}").argtypes = [_P, _P]
+            getattr(L, f"hsgo_elem_many_{suf}").argtypes = [_I32, _I64, _P, _P]
+            getattr(L, f"hsgo_heat_bath_draw_{suf}").argtypes = [_P, real, real, real, _P]
+            getattr(L, f"hsgo_elem_consts_{suf}").argtypes = [_P, _P, _P]
             fn = getattr(L, f"hsgo_sweep_{suf}")
             fn.argtypes = [_I32, _U64, _U64, _I32, _D, _I32, _I32, _I32, _I32, _P, _P, _P, _D,
                            _P, _P, _P]
@@ -81,6 +86,15 @@ def _ptr(a: np.ndarray):
 
 def _key(seed: int) -> np.ndarray:
     return np.array([seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF], dtype=np.uint32)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return int(lib().hsgo_threads())
+
+
+def set_threads(n: int) -> None:
+    lib().hsgo_set_threads(int(n))
 
 
 # ----------------------------------------------------------------------------- RNG
@@ -112,6 +126,35 @@ def sincos_2pi(u: float, dtype=np.float64):
     c = np.zeros(1, dtype=dtype)
     getattr(lib(), f"hsgo_sincos_2pi_{suf}")(float(np.dtype(dtype).type(u)), _ptr(s), _ptr(c))
     return s[0], c[0]
+
+
+_ELEM = {"exp": 0, "expm1": 1, "log": 2, "log1p": 3}
+
+
+def elem(name: str, x, dtype=np.float64) -> np.ndarray:
+    """The oracle's own exp / expm1 (x in [x_min, 0]), log (x > 0, normal) or log1p
+    (|x| <= 1/2), element-wise in the given precision."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=dtype).ravel())
+    out = np.empty_like(a)
+    getattr(lib(), f"hsgo_elem_many_{_suf(dtype)}")(_ELEM[name], a.size, _ptr(a), _ptr(out))
+    return out
+
+
+def elem_consts(dtype):
+    """(1/n! for n < 18, 1/(2j+1) for j < 18, [ln2 head, ln2 tail, log2 e, sqrt(1/2)])."""
+    e = np.empty(18, dtype=dtype)
+    a = np.empty(18, dtype=dtype)
+    l = np.empty(4, dtype=dtype)
+    getattr(lib(), f"hsgo_elem_consts_{_suf(dtype)}")(_ptr(e), _ptr(a), _ptr(l))
+    return e, a, l
+
+
+def heat_bath_draw(h, beta: float, u0: float, u1: float, dtype=np.float64) -> np.ndarray:
+    hh = np.ascontiguousarray(np.asarray(h, dtype=dtype))
+    out = np.zeros(3, dtype=dtype)
+    getattr(lib(), f"hsgo_heat_bath_draw_{_suf(dtype)}")(_ptr(hh), float(beta), float(u0),
+                                                         float(u1), _ptr(out))
+    return out
 
 
 def trial_spin(u0: float, u1: float, dtype=np.float64) -> np.ndarray:

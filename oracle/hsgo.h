@@ -55,6 +55,15 @@ void hsgo_u01_many(int64_t n, const uint32_t *w, double *out);
    k = 0..17, correctly rounded from binary128 arithmetic. */
 void hsgo_poly_coefs_f64(double out[18]);
 void hsgo_poly_coefs_f32(float out[18]);
+/* Constants of the own exp / log family: expm1[n] = 1/n!, atanh[j] = 1/(2j+1) for
+   n, j < 18, ln2 = {head of ln 2 (a multiple of 2^-16 in binary32, 2^-32 in binary64),
+   ln 2 - head, log2(e), sqrt(1/2)}; binary128 arithmetic rounded once. */
+void hsgo_elem_consts_f32(float expm1[18], float atanh[18], float ln2[4]);
+void hsgo_elem_consts_f64(double expm1[18], double atanh[18], double ln2[4]);
+
+/* OpenMP threads of the parallel loops (results do not depend on the count). */
+int hsgo_threads(void);
+void hsgo_set_threads(int n);
 
 /* Replica-exchange step over one temperature ladder (see hsgo_common.c). */
 int hsgo_pt_swap(int32_t n_temps, const double *beta_of_slot, const double *E_of_chain,
@@ -68,6 +77,12 @@ int hsgo_pt_swap(int32_t n_temps, const double *beta_of_slot, const double *E_of
   void hsgo_local_field_##SUF(int32_t L, const R *spins, const R *J, int32_t x, int32_t y,    \
                               int32_t z, R h[3]);                                             \
   void hsgo_overrelax_site_##SUF(const R h[3], R s[3]);                                       \
+  R hsgo_exp_##SUF(R x);                                                                      \
+  R hsgo_expm1_##SUF(R x);                                                                    \
+  R hsgo_log_##SUF(R x);                                                                      \
+  R hsgo_log1p_##SUF(R x);                                                                    \
+  void hsgo_heat_bath_draw_##SUF(const R h[3], R beta, R u0, R u1, R s[3]);                  \
+  void hsgo_elem_many_##SUF(int32_t which, int64_t n, const R *x, R *out);                   \
   int hsgo_sweep_##SUF(int32_t L, uint64_t seed, uint64_t sweep0, int32_t n_sweeps, double T, \
                        int32_t k_hits, int32_t n_or, int32_t renorm_every, int32_t heat_bath, \
                        R *spins, const R *J, double *E, double margin_eps, uint8_t *taint,    \

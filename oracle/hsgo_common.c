@@ -8,9 +8,15 @@
  * definition there.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stddef.h>
 #include "hsgo.h"
+
+/* Threads the oracle's parallel loops use (OpenMP), and a way to set them: the sweep's
+ * result does not depend on the count (sums are formed per plane, then in plane order). */
+int hsgo_threads(void) { return omp_get_max_threads(); }
+void hsgo_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 
 /* Philox4x32 with 10 rounds.  One round maps counter (c0,c1,c2,c3) and key
  * (k0,k1) through two 32x32->64 multiplications:
@@ -80,6 +86,50 @@ static void poly_coefs_q(__float128 out[18]) {
     if (k > 0) term = term * half_pi / k;
     out[k] = ((k / 2) % 2 == 0) ? term : -term;
   }
+}
+
+/* Constants of the own exp / log family, evaluated in binary128 and rounded once:
+ * expm1[n] = 1/n! (n = 2..17), atanh[j] = 1/(2j+1) (j = 1..17), and ln2[] = {head of
+ * ln 2 (ln 2 rounded to a multiple of 2^-split, so that e * head is exact for every
+ * exponent e of the format), tail (ln 2 - head), log2(e), sqrt(1/2)}. */
+static const __float128 LN2_Q = 0.693147180559945309417232121458176568075500134360255Q;
+static const __float128 SQRT_HALF_Q = 0.707106781186547524400844362104849039284835937688474Q;
+
+static void elem_consts_q(__float128 expm1[18], __float128 atanh[18]) {
+  __float128 f = 1;
+  for (int n = 0; n < 18; ++n) {
+    if (n > 0) f = f * n;
+    expm1[n] = 1 / f;
+    atanh[n] = (__float128)1 / (2 * n + 1);
+  }
+}
+
+void hsgo_elem_consts_f32(float expm1[18], float atanh[18], float ln2[4]) {
+  __float128 e[18], a[18];
+  elem_consts_q(e, a);
+  for (int n = 0; n < 18; ++n) {
+    expm1[n] = (float)e[n];
+    atanh[n] = (float)a[n];
+  }
+  const __float128 head = (__float128)(int64_t)(LN2_Q * 65536 + 0.5Q) / 65536; /* 2^-16 */
+  ln2[0] = (float)head;
+  ln2[1] = (float)(LN2_Q - head);
+  ln2[2] = (float)(1 / LN2_Q);
+  ln2[3] = (float)SQRT_HALF_Q;
+}
+
+void hsgo_elem_consts_f64(double expm1[18], double atanh[18], double ln2[4]) {
+  __float128 e[18], a[18];
+  elem_consts_q(e, a);
+  for (int n = 0; n < 18; ++n) {
+    expm1[n] = (double)e[n];
+    atanh[n] = (double)a[n];
+  }
+  const __float128 head = (__float128)(int64_t)(LN2_Q * 4294967296.0Q + 0.5Q) / 4294967296.0Q;
+  ln2[0] = (double)head;
+  ln2[1] = (double)(LN2_Q - head);
+  ln2[2] = (double)(1 / LN2_Q);
+  ln2[3] = (double)SQRT_HALF_Q;
 }
 
 void hsgo_poly_coefs_f64(double out[18]) {

@@ -32,6 +32,10 @@ HSG_PLANE_LAUNCH = 32
 HSG_STREAM_LOADS = 64
 HSG_PHASE_LAUNCH = 128
 HSG_PHASE_MC = 256
+# launch kinds reported by hsg_sweep_timed
+LAUNCH_OTHER, LAUNCH_MC_PASS, LAUNCH_OR_PASS, LAUNCH_OR_PHASE, LAUNCH_OR_PHASE_MC, \
+    LAUNCH_MARCH = range(6)
+LAUNCH_NAMES = ("other", "mc_pass", "or_pass", "or_phase", "or_phase_mc", "march")
 FUSED_MIN_L, FUSED_MAX_L = 256, 1024
 PHASE_MIN_L, PHASE_MAX_L = 64, 1024
 FOURIER_VALUES = 65
@@ -98,12 +102,15 @@ def lib() -> ctypes.CDLL:
         L.hsg_import.argtypes = [LP, P, P, P]
         L.hsg_export.argtypes = [LP, P, P, P]
         L.hsg_sweep.argtypes = [LP, ctypes.POINTER(_SweepParams), I32, P]
+        L.hsg_sweep_timed.argtypes = [LP, ctypes.POINTER(_SweepParams), I32, P, I32, P, P,
+                                      ctypes.POINTER(I32)]
         L.hsg_energy.argtypes = [LP, I32, P, P]
         L.hsg_overlap.argtypes = [LP, LP, P, P]
         L.hsg_overlap_fourier.argtypes = [LP, LP, P, P]
         L.hsg_last_error.restype = ctypes.c_char_p
         for name in ("hsg_lattice_bytes", "hsg_init_lattice", "hsg_import", "hsg_export",
-                     "hsg_sweep", "hsg_energy", "hsg_overlap", "hsg_overlap_fourier"):
+                     "hsg_sweep", "hsg_sweep_timed", "hsg_energy", "hsg_overlap",
+                     "hsg_overlap_fourier"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -210,6 +217,23 @@ class Lattice:
                          (HSG_HEAT_BATH if heat_bath else 0) | f)
         check(lib().hsg_sweep(ctypes.byref(self._d), ctypes.byref(p), int(n_sweeps),
                               _stream(stream)))
+
+    def sweep_timed(self, T: float, k: int = 1, n_or: int = 0, renorm_every: int = 0,
+                    n_sweeps: int = 1, heat_bath: bool = False, flags: int | None = None,
+                    capacity: int = 4096, stream=None) -> list[tuple[int, float]]:
+        """As sweep(), with every launch timed by HIP events on the launch stream:
+        [(launch kind, ms)] in launch order (hsg_sweep_timed; waits for the stream)."""
+        import numpy as np
+        f = default_flags(self.L, self.dtype) if flags is None else int(flags)
+        p = _SweepParams(float(T), int(k), int(n_or), int(renorm_every),
+                         (HSG_HEAT_BATH if heat_bath else 0) | f)
+        kinds = np.zeros(capacity, dtype=np.int32)
+        ms = np.zeros(capacity, dtype=np.float32)
+        n = ctypes.c_int32()
+        check(lib().hsg_sweep_timed(ctypes.byref(self._d), ctypes.byref(p), int(n_sweeps),
+                                    _stream(stream), capacity, kinds.ctypes.data_as(ctypes.c_void_p),
+                                    ms.ctypes.data_as(ctypes.c_void_p), ctypes.byref(n)))
+        return [(int(kinds[i]), float(ms[i])) for i in range(n.value)]
 
     # ---------------------------------------------------------- observables
     def energy(self, recompute: bool = False, stream=None) -> torch.Tensor:

@@ -51,6 +51,41 @@ int check_lattice(const hsg_lattice* lat) {
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+// Launch recorder of hsg_sweep_timed: while one is set (per calling thread), every
+// launch of a sweep is bracketed by two events recorded on the launch stream, up to
+// `capacity` launches; later launches run unrecorded.
+struct LaunchRecorder {
+  int32_t capacity = 0, count = 0;
+  int32_t* kinds = nullptr;
+  std::vector<hipEvent_t> events;  // 2 per recorded launch
+  hipError_t err = hipSuccess;     // first event failure
+};
+thread_local LaunchRecorder* g_recorder = nullptr;
+
+// Enqueues launch() (returning hipError_t), bracketed by events when a recorder is set.
+template <class F>
+hipError_t recorded(int32_t kind, hipStream_t st, F&& launch) {
+  LaunchRecorder* r = g_recorder;
+  if (!r || r->count >= r->capacity || r->err != hipSuccess) return launch();
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+  if (e != hipSuccess) {
+    for (hipEvent_t x : ev)
+      if (x) (void)hipEventDestroy(x);
+    r->err = e;
+    return launch();
+  }
+  const hipError_t le = launch();
+  e = hipEventRecord(ev[1], st);
+  r->events.push_back(ev[0]);
+  r->events.push_back(ev[1]);
+  r->kinds[r->count++] = kind;
+  if (e != hipSuccess) r->err = e;
+  return le;
+}
+
 int check_params(const hsg_sweep_params* p) {
   if (!p) return fail(HSG_EINVAL, "sweep parameters are NULL");
   if (!(p->T > 0.0)) return fail(HSG_EINVAL, "T must be > 0 (INFINITY for beta = 0), got %g", p->T);
@@ -84,8 +119,11 @@ bool renorm_due(const hsg_sweep_params* p, uint64_t sweep) {
 // Pass-by-pass schedule: one launch per colour pass over the whole lattice, or with
 // HSG_PLANE_LAUNCH one launch per z slab of tiles (one z plane from L = 64 up).  With
 // HSG_PHASE_LAUNCH each over-relaxation phase is one launch reading one spin array and
-// writing the other (the lattice's and the work buffer's second one); after an odd
-// number of them the spins are copied back at the end of the call.  With HSG_PHASE_MC
+// writing the other (the lattice's and the work buffer's second one); when a call would
+// run an odd number of them, its last phase (never one that carries a Monte Carlo pass)
+// runs as two colour passes in place instead, so the spins end in the lattice's own
+// array without a copy (two passes cost less than a phase launch plus a copy of the
+// lattice).  With HSG_PHASE_MC
 // the launch of a sweep's last over-relaxation phase also runs the colour-0 Monte Carlo
 // pass of the next sweep of the call (and the renormalisation between them when due);
 // that sweep then starts with its colour-1 pass.
@@ -100,6 +138,9 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   const bool phase_launch =
       (p->flags & (HSG_PHASE_LAUNCH | HSG_PHASE_MC)) && phase_supported(lat->L);
   const bool phase_mc = phase_launch && (p->flags & HSG_PHASE_MC) && p->k_hits > 0;
+  // an odd count of phase launches: the call's last phase runs as colour passes
+  const bool last_as_passes =
+      phase_launch && (((int64_t)n_sweeps * p->n_or) & 1) != 0;
   PhaseArgs<R> ph{};
   ph.J = (const R*)lat->J;
   ph.beta = (R)(1.0 / p->T);
@@ -131,7 +172,8 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
     for (int32_t phase = 0; phase <= p->n_or; ++phase) {
       if (phase == 0 && p->k_hits == 0) continue;
       a.phase = (uint32_t)phase;
-      if (phase_launch && phase > 0) {
+      const bool last_phase = n + 1 == n_sweeps && phase == p->n_or;
+      if (phase_launch && phase > 0 && !(last_as_passes && last_phase)) {
         const bool then_mc = phase_mc && phase == p->n_or && n + 1 < n_sweeps;
         ph.in = bufs[cur];
         ph.out = bufs[1 - cur];
@@ -140,7 +182,10 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
         ph.then_mc = then_mc ? 1 : 0;
         ph.mc_sweep = (uint32_t)(sweep + 1);
         ph.renorm = then_mc && renorm_due(p, sweep) ? 1 : 0;
-        int rc = device_status(launch_phase<R>(ph, st), "phase launch");
+        int rc = device_status(
+            recorded(then_mc ? HSG_LAUNCH_OR_PHASE_MC : HSG_LAUNCH_OR_PHASE, st,
+                     [&] { return launch_phase<R>(ph, st); }),
+            "phase launch");
         if (rc) return rc;
         cur = 1 - cur;
         a.spins = planes_of<R>(bufs[cur], Nh);
@@ -161,7 +206,10 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
         if (!by_slab) {
           a.tile_base = 0;
           a.tile_count = g.n_blocks;
-          int rc = device_status(launch_colour_pass<R>(mode, a, st), "colour pass");
+          int rc = device_status(
+              recorded(mode == PassMode::OverRelax ? HSG_LAUNCH_OR_PASS : HSG_LAUNCH_MC_PASS, st,
+                       [&] { return launch_colour_pass<R>(mode, a, st); }),
+              "colour pass");
           if (rc) return rc;
           continue;
         }
@@ -169,22 +217,22 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
           const int32_t tz = a.reverse ? g.tiles_z - 1 - i : i;
           a.tile_base = tz * slab_tiles;
           a.tile_count = slab_tiles;
-          int rc = device_status(launch_colour_pass<R>(mode, a, st), "colour pass (slab)");
+          int rc = device_status(
+              recorded(mode == PassMode::OverRelax ? HSG_LAUNCH_OR_PASS : HSG_LAUNCH_MC_PASS, st,
+                       [&] { return launch_colour_pass<R>(mode, a, st); }),
+              "colour pass (slab)");
           if (rc) return rc;
         }
       }
     }
     if (renorm_due(p, sweep) && !renorm_done) {
-      int rc = device_status(launch_renormalise<R>(lat->L, bufs[cur], 2, st), "renormalise");
+      int rc = device_status(recorded(HSG_LAUNCH_OTHER, st,
+                                      [&] { return launch_renormalise<R>(lat->L, bufs[cur], 2, st); }),
+                             "renormalise");
       if (rc) return rc;
     }
   }
-  if (cur != 0) {
-    const size_t bytes = (size_t)3 * lat->L * lat->L * lat->L * sizeof(R);
-    int rc = device_status(hipMemcpyAsync(bufs[0], bufs[1], bytes, hipMemcpyDeviceToDevice, st),
-                           "copy spins");
-    if (rc) return rc;
-  }
+  if (cur != 0) return fail(HSG_EDEVICE, "internal: spins left in the second array");
   return HSG_OK;
 }
 
@@ -236,7 +284,9 @@ int sweep_fused(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
     }
     a.in = bufs[cur];
     a.out = bufs[1 - cur];
-    int rc = device_status(launch_march<R>(a, (int32_t)n, st), "fused passes");
+    int rc = device_status(
+        recorded(HSG_LAUNCH_MARCH, st, [&] { return launch_march<R>(a, (int32_t)n, st); }),
+        "fused passes");
     if (rc) return rc;
     cur = 1 - cur;
     g += n;
@@ -265,8 +315,12 @@ int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hi
                              : sweep_plain<R>(lat, p, n_sweeps, st);
   if (rc) return rc;
   if (n_sweeps > 0 && p->k_hits > 0) {
-    rc = device_status(launch_fold_partials(pass_partials(lat->work),
-                                            pass_geometry(lat->L).n_blocks, lat->E, st),
+    rc = device_status(recorded(HSG_LAUNCH_OTHER, st,
+                                [&] {
+                                  return launch_fold_partials(pass_partials(lat->work),
+                                                              pass_geometry(lat->L).n_blocks,
+                                                              lat->E, st);
+                                }),
                        "fold");
     if (rc) return rc;
   }
@@ -346,7 +400,39 @@ int hsg_export(const hsg_lattice* lat, void* canon_spins, void* canon_J, void* s
                        "export");
 }
 
+static int sweep_checked(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps,
+                         void* stream);
+
 int hsg_sweep(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, void* stream) {
+  return sweep_checked(lat, p, n_sweeps, stream);
+}
+
+int hsg_sweep_timed(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, void* stream,
+                    int32_t capacity, int32_t* kinds, float* ms, int32_t* n_recorded) {
+  if (capacity < 0 || (capacity > 0 && (!kinds || !ms)) || !n_recorded)
+    return fail(HSG_EINVAL, "hsg_sweep_timed: bad capacity or output arrays");
+  if (g_recorder) return fail(HSG_EINVAL, "hsg_sweep_timed: nested call");
+  LaunchRecorder rec;
+  rec.capacity = capacity;
+  rec.kinds = kinds;
+  rec.events.reserve((size_t)2 * (size_t)capacity);
+  g_recorder = &rec;
+  int rc = sweep_checked(lat, p, n_sweeps, stream);
+  g_recorder = nullptr;
+  *n_recorded = rec.count;
+  if (rc == HSG_OK && rec.err != hipSuccess) rc = device_status(rec.err, "timing events");
+  if (rc == HSG_OK && rec.count > 0)
+    rc = device_status(hipEventSynchronize(rec.events.back()), "timing events");
+  for (int32_t i = 0; rc == HSG_OK && i < rec.count; ++i)
+    rc = device_status(hipEventElapsedTime(&ms[i], rec.events[2 * i], rec.events[2 * i + 1]),
+                       "timing events");
+  if (rc != HSG_OK) (void)hipStreamSynchronize(as_stream(stream));  // events idle before destroy
+  for (hipEvent_t e : rec.events) (void)hipEventDestroy(e);
+  return rc;
+}
+
+static int sweep_checked(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps,
+                         void* stream) {
   int rc = check_lattice(lat);
   if (rc) return rc;
   rc = check_params(p);

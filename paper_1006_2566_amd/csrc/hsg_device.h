@@ -134,16 +134,140 @@ __device__ __forceinline__ float dev_sqrt(float a) { return sqrtf(a); }
 __device__ __forceinline__ double dev_sqrt(double a) { return sqrt(a); }
 __device__ __forceinline__ float dev_div(float a, float b) { return __fdiv_rn(a, b); }
 __device__ __forceinline__ double dev_div(double a, double b) { return __ddiv_rn(a, b); }
-__device__ __forceinline__ float dev_exp(float a) { return expf(a); }
-__device__ __forceinline__ double dev_exp(double a) { return exp(a); }
-__device__ __forceinline__ float dev_log(float a) { return logf(a); }
-__device__ __forceinline__ double dev_log(double a) { return log(a); }
-__device__ __forceinline__ float dev_log1p(float a) { return log1pf(a); }
-__device__ __forceinline__ double dev_log1p(double a) { return log1p(a); }
-__device__ __forceinline__ float dev_expm1(float a) { return expm1f(a); }
-__device__ __forceinline__ double dev_expm1(double a) { return expm1(a); }
 __device__ __forceinline__ float dev_rint(float a) { return rintf(a); }
 __device__ __forceinline__ double dev_rint(double a) { return rint(a); }
+
+// Own exp, expm1, log and log1p for the heat-bath draw and the Gaussian couplings: a
+// fixed sequence of correctly rounded operations, so that results do not depend on a
+// math library's last bits.  Methods:
+//  - exp, expm1 on [kXMin, 0]: Cody and Waite's reduction (Software Manual for the
+//    Elementary Functions, 1980), x = k ln2 + r with |r| <= ln2/2 and ln 2 split into a
+//    head (a multiple of 2^-16 in binary32, 2^-32 in binary64, so k * head is exact) and
+//    a tail; expm1(r) = r + r^2 (1/2! + r (1/3! + ...)) (Taylor, to r^8 / r^13);
+//    exp(x) = 2^k (1 + expm1(r)), expm1(x) = 2^k expm1(r) + (2^k - 1), one rounding
+//    each.  Smaller inputs are raised to kXMin (the results stay normal).
+//  - log on normal positive x: x = 2^e m, m in [sqrt(1/2), sqrt(2)),
+//    log x = e ln2 + 2 atanh((m - 1) / (m + 1)); log1p on |x| <= 1/2: 2 atanh(x / (2 + x));
+//    2 atanh(f) = 2f + 2f f^2 (1/3 + f^2 (1/5 + ...)) (Taylor, to f^15 / f^35).
+// Coefficients: 1/n! and 1/(2j+1) correctly rounded.  Within 2 ulp of the true values.
+template <typename R>
+struct Elem;
+
+template <>
+struct Elem<float> {
+  static constexpr float kXMin = -80.0f;
+  static constexpr float kLn2Hi = 0x1.62e4p-1f, kLn2Lo = 0x1.7f7d1cp-20f;
+  static constexpr float kLog2e = 0x1.715476p+0f, kSqrtHalf = 0x1.6a09e6p-1f;
+  __device__ __forceinline__ static float expm1_poly(float r) {  // sum_{n>=2} r^(n-2)/n!
+    float q = 0x1.a01a02p-16f;       // 1/8!
+    q = fmaf(q, r, 0x1.a01a02p-13f);  // 1/7!
+    q = fmaf(q, r, 0x1.6c16c2p-10f);  // 1/6!
+    q = fmaf(q, r, 0x1.111112p-7f);   // 1/5!
+    q = fmaf(q, r, 0x1.555556p-5f);   // 1/4!
+    q = fmaf(q, r, 0x1.555556p-3f);   // 1/3!
+    return fmaf(q, r, 0x1p-1f);       // 1/2!
+  }
+  __device__ __forceinline__ static float atanh_poly(float s) {  // sum_{j>=1} s^(j-1)/(2j+1)
+    float q = 0x1.111112p-4f;         // 1/15
+    q = fmaf(q, s, 0x1.3b13b2p-4f);   // 1/13
+    q = fmaf(q, s, 0x1.745d18p-4f);   // 1/11
+    q = fmaf(q, s, 0x1.c71c72p-4f);   // 1/9
+    q = fmaf(q, s, 0x1.24924ap-3f);   // 1/7
+    q = fmaf(q, s, 0x1.99999ap-3f);   // 1/5
+    return fmaf(q, s, 0x1.555556p-2f);  // 1/3
+  }
+  __device__ __forceinline__ static float frexp_(float x, int& e) { return frexpf(x, &e); }
+  __device__ __forceinline__ static float ldexp_(float x, int e) { return ldexpf(x, e); }
+};
+
+template <>
+struct Elem<double> {
+  static constexpr double kXMin = -700.0;
+  static constexpr double kLn2Hi = 0x1.62e42ffp-1, kLn2Lo = -0x1.718432a1b0e26p-35;
+  static constexpr double kLog2e = 0x1.71547652b82fep+0, kSqrtHalf = 0x1.6a09e667f3bcdp-1;
+  __device__ __forceinline__ static double expm1_poly(double r) {
+    double q = 0x1.6124613a86d09p-33;   // 1/13!
+    q = fma(q, r, 0x1.1eed8eff8d898p-29);  // 1/12!
+    q = fma(q, r, 0x1.ae64567f544e4p-26);  // 1/11!
+    q = fma(q, r, 0x1.27e4fb7789f5cp-22);  // 1/10!
+    q = fma(q, r, 0x1.71de3a556c734p-19);  // 1/9!
+    q = fma(q, r, 0x1.a01a01a01a01ap-16);  // 1/8!
+    q = fma(q, r, 0x1.a01a01a01a01ap-13);  // 1/7!
+    q = fma(q, r, 0x1.6c16c16c16c17p-10);  // 1/6!
+    q = fma(q, r, 0x1.1111111111111p-7);   // 1/5!
+    q = fma(q, r, 0x1.5555555555555p-5);   // 1/4!
+    q = fma(q, r, 0x1.5555555555555p-3);   // 1/3!
+    return fma(q, r, 0x1p-1);              // 1/2!
+  }
+  __device__ __forceinline__ static double atanh_poly(double s) {
+    double q = 0x1.d41d41d41d41dp-6;     // 1/35
+    q = fma(q, s, 0x1.f07c1f07c1f08p-6);  // 1/33
+    q = fma(q, s, 0x1.0842108421084p-5);  // 1/31
+    q = fma(q, s, 0x1.1a7b9611a7b96p-5);  // 1/29
+    q = fma(q, s, 0x1.2f684bda12f68p-5);  // 1/27
+    q = fma(q, s, 0x1.47ae147ae147bp-5);  // 1/25
+    q = fma(q, s, 0x1.642c8590b2164p-5);  // 1/23
+    q = fma(q, s, 0x1.8618618618618p-5);  // 1/21
+    q = fma(q, s, 0x1.af286bca1af28p-5);  // 1/19
+    q = fma(q, s, 0x1.e1e1e1e1e1e1ep-5);  // 1/17
+    q = fma(q, s, 0x1.1111111111111p-4);  // 1/15
+    q = fma(q, s, 0x1.3b13b13b13b14p-4);  // 1/13
+    q = fma(q, s, 0x1.745d1745d1746p-4);  // 1/11
+    q = fma(q, s, 0x1.c71c71c71c71cp-4);  // 1/9
+    q = fma(q, s, 0x1.2492492492492p-3);  // 1/7
+    q = fma(q, s, 0x1.999999999999ap-3);  // 1/5
+    return fma(q, s, 0x1.5555555555555p-2);  // 1/3
+  }
+  __device__ __forceinline__ static double frexp_(double x, int& e) { return frexp(x, &e); }
+  __device__ __forceinline__ static double ldexp_(double x, int e) { return ldexp(x, e); }
+};
+
+// exp(x) = scale (1 + p), scale = 2^k, for x in [kXMin, 0] (smaller x raised to kXMin).
+template <typename R>
+__device__ __forceinline__ void own_exp_parts(R x, R& scale, R& p) {
+  using E = Elem<R>;
+  x = x < E::kXMin ? E::kXMin : x;
+  const R k = dev_rint(x * E::kLog2e);
+  R r = dev_fma(-k, E::kLn2Hi, x);
+  r = dev_fma(-k, E::kLn2Lo, r);
+  p = dev_fma(r * r, E::expm1_poly(r), r);
+  scale = E::ldexp_((R)1, (int)k);
+}
+template <typename R>
+__device__ __forceinline__ R own_exp(R x) {
+  R scale, p;
+  own_exp_parts(x, scale, p);
+  return dev_fma(scale, p, scale);
+}
+template <typename R>
+__device__ __forceinline__ R own_expm1(R x) {
+  R scale, p;
+  own_exp_parts(x, scale, p);
+  return dev_fma(scale, p, scale - (R)1);
+}
+// 2 atanh(f), |f| <= 1/3.
+template <typename R>
+__device__ __forceinline__ R own_atanh2(R f) {
+  const R s = f * f, t = f + f;
+  return dev_fma(t * s, Elem<R>::atanh_poly(s), t);
+}
+template <typename R>
+__device__ __forceinline__ R own_log1p(R x) {  // |x| <= 1/2
+  return own_atanh2(dev_div(x, (R)2 + x));
+}
+template <typename R>
+__device__ __forceinline__ R own_log(R x) {  // x positive and normal
+  using E = Elem<R>;
+  int e;
+  R m = E::frexp_(x, e);  // m in [1/2, 1)
+  if (m < E::kSqrtHalf) {
+    m = m + m;
+    e -= 1;
+  }
+  const R lm = own_atanh2(dev_div(m - (R)1, m + (R)1));
+  const R ef = (R)e;
+  return dev_fma(ef, E::kLn2Hi, dev_fma(ef, E::kLn2Lo, lm));
+}
 
 // Metropolis acceptance exp(x) for x = -beta dE.  Binary32 uses the hardware 2^y
 // (v_exp_f32, within 1 ulp) at y = x log2(e): the result is within 2e-8 of exp(x)
@@ -263,8 +387,8 @@ __device__ __forceinline__ Vec3<float> sphere_point_words<float>(uint32_t w0, ui
 // Exact draw from the conditional law exp(beta sigma.h) on the sphere.  With
 // a = beta |h|, w = 1 - u0 and q = 1 - e^{-2a}, the cosine to the field is
 // c = 1 + log(1 - w q)/a, evaluated as log1p(-w q) while w q <= 1/2 and as
-// log(u0 + w e^{-2a}) (one fused multiply-add, no cancellation) above; c = 2 u0 - 1
-// for a = 0.  The azimuth is 2 pi u1, and the tangent frame about n = h/|h| is the
+// log(u0 + w e^{-2a}) (one fused multiply-add, no cancellation) above (the own exp,
+// expm1, log and log1p above); c = 2 u0 - 1 for a = 0.  The azimuth is 2 pi u1, and the tangent frame about n = h/|h| is the
 // branch-free orthonormal basis of Duff et al. (JCGT 2017).
 template <typename R>
 __device__ __forceinline__ Vec3<R> heat_bath_point(const Vec3<R>& h, R beta, R u0, R u1) {
@@ -274,8 +398,8 @@ __device__ __forceinline__ Vec3<R> heat_bath_point(const Vec3<R>& h, R beta, R u
   R c;
   if (a > (R)0) {
     const R w = (R)1 - u0;
-    const R wq = w * -dev_expm1((R)-2 * a);
-    const R lg = wq <= (R)0.5 ? dev_log1p(-wq) : dev_log(dev_fma(w, dev_exp((R)-2 * a), u0));
+    const R wq = w * -own_expm1((R)-2 * a);
+    const R lg = wq <= (R)0.5 ? own_log1p(-wq) : own_log(dev_fma(w, own_exp((R)-2 * a), u0));
     c = (R)1 + dev_div(lg, a);
   } else {
     c = (R)2 * u0 - (R)1;

@@ -48,11 +48,11 @@ __device__ __forceinline__ void init_site(int32_t L, int64_t e, uint32_t k0, uin
   if (!J) return;
   const Word4 wj = philox10(0u, st.canon, 0u, kTagInitJ, jk0, jk1);
   R sn, cs;
-  const R r01 = dev_sqrt((R)-2 * dev_log(unit_uniform<R>(wj.w0)));
+  const R r01 = dev_sqrt((R)-2 * own_log(unit_uniform<R>(wj.w0)));
   sincos_2pi(unit_uniform<R>(wj.w1), sn, cs);
   J[base] = r01 * cs;
   J[base + Nh] = r01 * sn;
-  const R r23 = dev_sqrt((R)-2 * dev_log(unit_uniform<R>(wj.w2)));
+  const R r23 = dev_sqrt((R)-2 * own_log(unit_uniform<R>(wj.w2)));
   sincos_2pi(unit_uniform<R>(wj.w3), sn, cs);
   J[base + 2 * Nh] = r23 * cs;
 }
@@ -83,18 +83,27 @@ struct HitCtx {
 // decisions, only its accept/reject step does; with G > 1 a group's trials are formed
 // first (instruction-level parallelism for a wave with few neighbours on its SIMD),
 // then its decisions in order.  Every operation and the order of the energy sum are
-// the same for any G.
+// the same for any G.  A heat-bath draw is always taken and does not depend on the spin
+// it replaces, so of k draws only the last counts and only that one is computed.
 template <typename R, PassMode MODE, int G = 1>
 __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uint32_t site,
                                                const HitCtx<R>& hc) {
   double dE_sum = 0.0;
   if constexpr (MODE == PassMode::OverRelax) {
     s = reflect(s, h);
+  } else if constexpr (MODE == PassMode::HeatBath) {
+    const uint32_t j = (uint32_t)hc.k_hits - 1u;  // the last draw: uniforms 2j, 2j + 1
+    const Word4 x = philox10(hc.sweep, site, (hc.phase << 16) | (j >> 1), kTagHeatBath,
+                             hc.seed_lo, hc.seed_hi);
+    const uint32_t w0 = (j & 1u) ? x.w2 : x.w0, w1 = (j & 1u) ? x.w3 : x.w1;
+    const Vec3<R> t = heat_bath_point(h, hc.beta, unit_uniform<R>(w0), unit_uniform<R>(w1));
+    const R dE = dot3(s, h) - dot3(t, h);
+    s = t;
+    dE_sum = (double)dE;
   } else {
-    constexpr bool kMH = MODE == PassMode::Metropolis;
-    constexpr uint32_t tag = kMH ? kTagMetropolis : kTagHeatBath;
-    constexpr int U = kMH ? 3 : 2;   // uniforms per hit
-    constexpr int H = kMH ? 4 : 2;   // hits per group
+    constexpr uint32_t tag = kTagMetropolis;
+    constexpr int U = 3;             // uniforms per hit
+    constexpr int H = 4;             // hits per group
     constexpr int NB = U * H / 4;    // Philox blocks per group
     R sh = dot3(s, h);
     uint32_t b0 = 0;
@@ -115,19 +124,13 @@ __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uin
       Vec3<R> trial[H];
       R th[H], u2[H];
       auto draw = [&](int g) {
-        if constexpr (kMH) {
-          trial[g] = sphere_point_words<R>(w[U * g], w[U * g + 1]);
-          u2[g] = unit_uniform<R>(w[U * g + 2]);
-        } else {
-          trial[g] = heat_bath_point(h, hc.beta, unit_uniform<R>(w[U * g]),
-                                     unit_uniform<R>(w[U * g + 1]));
-        }
+        trial[g] = sphere_point_words<R>(w[U * g], w[U * g + 1]);
+        u2[g] = unit_uniform<R>(w[U * g + 2]);
         th[g] = dot3(trial[g], h);
       };
       auto decide = [&](int g) {
         const R dE = sh - th[g];
-        bool accept = true;
-        if constexpr (kMH) accept = (dE <= (R)0) || (u2[g] < accept_prob(-hc.beta * dE));
+        const bool accept = (dE <= (R)0) || (u2[g] < accept_prob(-hc.beta * dE));
         if (accept) {
           s = trial[g];
           sh = th[g];

@@ -57,6 +57,8 @@ class Result:
     arrival: float
     admitted: float
     finished: float
+    admitted_step: int = -1  # scheduler iteration of admission
+    finished_step: int = -1  # scheduler iteration that saw the lattice finished
 
     @property
     def latency(self) -> float:
@@ -185,7 +187,9 @@ class Server:
                          self.E.data_ptr(), self.sweep_ctr.data_ptr(),
                          self.remaining.data_ptr(), self.order.data_ptr(), 256, 0)
         self.free_slots = list(range(n_slots - 1, -1, -1))
-        self.active: dict[int, tuple[Request, int, int, float]] = {}  # slot -> (req, s_off, j_off, t_admit)
+        # slot -> (request, spin offset, coupling offset, admission time, admission iteration)
+        self.active: dict[int, tuple[Request, int, int, float, int]] = {}
+        self._it = 0  # scheduler iteration of run()
         self.tiles_dev = None
         self.n_tiles = 0
         self._tiles_dirty = True
@@ -244,7 +248,7 @@ class Server:
         slot = self.free_slots.pop()
         self.table[slot] = (s_off, j_off, req.seed, req.seed, req.L, req.k, 0, 0, HSG_CHAIN_INIT_J,
                             0)
-        self.active[slot] = (req, s_off, j_off, now)
+        self.active[slot] = (req, s_off, j_off, now, self._it)
         return True
 
     def _init_new(self, slots: list[int]) -> None:
@@ -318,8 +322,8 @@ class Server:
         m_pin, E_pin = both[:, :3], both[:, 3]
         info = []
         for s in done:
-            req, s_off, j_off, t_adm = self.active.pop(s)
-            info.append((req, t_adm))
+            req, s_off, j_off, t_adm, it_adm = self.active.pop(s)
+            info.append((req, t_adm, it_adm, self._it))
             self.arena_s.release(s_off, 3 * req.spins)
             self.arena_j.release(j_off, 3 * req.spins)
             self._set_dummy(s)
@@ -333,8 +337,9 @@ class Server:
         ev, info, m_pin, E_pin = rec
         ev.synchronize()
         m, E = m_pin.numpy().copy(), E_pin.numpy().copy()
-        return [Result(req.rid, float(E[i]), m[i].copy(), req.arrival, t_adm, t_done)
-                for i, (req, t_adm) in enumerate(info)]
+        return [Result(req.rid, float(E[i]), m[i].copy(), req.arrival, t_adm, t_done, it_adm,
+                       it_fin)
+                for i, (req, t_adm, it_adm, it_fin) in enumerate(info)]
 
     # -------------------------------------------------------------------- loop
     def run(self, trace: list[Request], realtime: bool = True) -> list[Result]:
@@ -359,6 +364,7 @@ class Server:
         prev = None       # (buffer, event, {slot: request id}) of the step in flight
         retiring = []     # (record, detection time) of read-backs in flight
         it = 0
+        self._it = 0
         self._table_dirty = False
         while pending or queue or self.active or prev is not None or retiring:
             c0 = clock()
@@ -411,6 +417,7 @@ class Server:
                 st["t_retire"] += clock() - c3
             prev = cur
             it += 1
+            self._it = it
             if prev is None and not retiring and not self.active:
                 if queue:
                     raise RuntimeError(f"request {queue[0].rid} does not fit the HBM budget")

@@ -253,3 +253,23 @@ def test_default_flags(hsg):
     assert hsg.default_flags(128, torch.float32) == hsg.HSG_SNAKE
     assert hsg.default_flags(320) == hsg.HSG_SNAKE | hsg.HSG_PHASE_MC
     assert hsg.default_flags(288) == hsg.HSG_SNAKE  # not a multiple of 64
+
+
+def test_sweep_timed_rejects_bad_outputs(hsg):
+    """The measurement form validates its output arrays before anything is enqueued,
+    and invalid sweep arguments fail as in hsg_sweep."""
+    lib = hsg.lib()
+    d = _desc(hsg)
+    p = hsg._SweepParams(1.0, 1, 0, 0, 0)
+    n = ctypes.c_int32(-5)
+    assert lib.hsg_sweep_timed(ctypes.byref(d), ctypes.byref(p), 1, None, -1, None, None,
+                               ctypes.byref(n)) == -1
+    assert lib.hsg_sweep_timed(ctypes.byref(d), ctypes.byref(p), 1, None, 4, None, None,
+                               ctypes.byref(n)) == -1
+    assert lib.hsg_sweep_timed(ctypes.byref(d), ctypes.byref(p), 1, None, 0, None, None,
+                               None) == -1
+    bad = hsg._SweepParams(-1.0, 1, 0, 0, 0)
+    assert lib.hsg_sweep_timed(ctypes.byref(d), ctypes.byref(bad), 1, None, 0, None, None,
+                               ctypes.byref(n)) == -1
+    assert b"T must be" in lib.hsg_last_error()
+    assert n.value == 0  # nothing was recorded
