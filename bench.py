@@ -106,7 +106,7 @@ def parse():
                     help="skip timing the Fourier-overlap records (chi_SG, xi inputs)")
     ap.add_argument("--counters", action="store_true",
                     help="short run for hardware-counter collection: one 1 GiB device copy "
-                         "(calibrates FETCH_SIZE / WRITE_SIZE), then 3 sweeps of the headline "
+                         "(calibrates FETCH_SIZE / WRITE_SIZE), then 4 sweeps of the headline "
                          "configuration; prints no JSON")
     ap.add_argument("--reduce-counters", nargs="+", metavar="CSV",
                     help="FETCH_CSV WRITE_CSV [ISSUE_CSV [TRACE_CSV]]: turn the "
@@ -651,7 +651,9 @@ def main():
         torch.cuda.synchronize()
         b.copy_(a)  # 1 GiB read + 1 GiB written
         torch.cuda.synchronize()
-        lat.sweep(T=args.T, k=args.k, n_or=args.n_or, renorm_every=R, n_sweeps=3, flags=flags)
+        # four sweeps (an even number of phase launches): three launches carrying the next
+        # colour-0 Metropolis pass, one plain phase, five Metropolis colour passes
+        lat.sweep(T=args.T, k=args.k, n_or=args.n_or, renorm_every=R, n_sweeps=4, flags=flags)
         torch.cuda.synchronize()
         return
 
