@@ -87,8 +87,10 @@ def parse():
                          "0 skips that leg")
     ap.add_argument("--batch-threads", type=int, default=0,
                     help="workgroup size of the batched sweep (0 = autotuned)")
-    ap.add_argument("--serve-requests", type=int, default=1000,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the served stream (0 skips that leg)")
+    ap.add_argument("--no-serve-load-sweep", dest="serve_load_sweep", action="store_false",
+                    help="skip the served streams at 100 and 50 requests per second")
     ap.add_argument("--serve-budget-mb", type=int, default=8192,
                     help="device memory for resident lattices of the served stream")
     ap.add_argument("--serve-step", type=int, default=16, help="sweeps per scheduling step")
@@ -399,9 +401,13 @@ def served_leg(args, torch):
     """Request stream: Poisson arrivals at 200 per second, L uniform in
     {8,16,32,64,96}, T uniform in [0.1,1], sweeps log-uniform in [100,10000], k in
     {1,4}, binary32, admitted by device-memory footprint, lattices resident between
-    steps, continuous batching; latency = completion - arrival (wall clock)."""
-    import numpy as np
-
+    steps, continuous batching; latency = completion - arrival (wall clock).  The same
+    kind of stream at 100 and 50 requests per second measures latency below saturation
+    (offered load / delivered capacity = rho).  Baseline: the same requests one after
+    another through plain per-lattice calls (initial state, sweeps with hsg_sweep,
+    energy read back) -- every 10th request of the 200/s trace, a systematic sample of
+    the whole trace."""
+    import paper_1006_2566_amd as hsg
     from paper_1006_2566_amd import serve as S
 
     trace = S.poisson_trace(n=args.serve_requests, rate=200.0, seed=1)
@@ -409,19 +415,37 @@ def served_leg(args, torch):
     if not args.serve_tile and not args.no_autotune:
         from paper_1006_2566_amd import autotune
         tile = autotune.serve_shape(trace[:64])["tile_sites"]
-    srv = S.Server(hbm_budget=args.serve_budget_mb << 20, n_slots=2048,
-                   step_sweeps=args.serve_step, tile_sites=tile)
-    srv.run([S.Request(rid=-1, seed=1, L=8, T=1.0, sweeps=2, k=1)], realtime=False)  # load kernels
-    t0 = time.perf_counter()
-    res = srv.run(trace, realtime=True)
-    wall = time.perf_counter() - t0
-    upd = float(sum(r.L ** 3 * r.sweeps * r.k for r in trace))
-    offered = upd / trace[-1].arrival / 1e9
-    st = S.latency_stats(res)
-    # the same kind of requests through the plain per-lattice path, one after another
-    # (initial state, sweeps with hsg_sweep, energy read back): the first 40 of the trace
-    import paper_1006_2566_amd as hsg
-    sample = trace[:40]
+
+    def serve(tr):
+        srv = S.Server(hbm_budget=args.serve_budget_mb << 20, n_slots=2048,
+                       step_sweeps=args.serve_step, tile_sites=tile)
+        srv.run([S.Request(rid=-1, seed=1, L=8, T=1.0, sweeps=2, k=1)], realtime=False)
+        t0 = time.perf_counter()
+        res = srv.run(tr, realtime=True)
+        wall = time.perf_counter() - t0
+        work = float(sum(r.L ** 3 * r.sweeps * r.k for r in tr))
+        st = S.latency_stats(res)
+        return {"requests": len(tr), "rate_per_s": len(tr) / tr[-1].arrival,
+                "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
+                "mean_latency_s": st["mean_s"], "wall_s": wall,
+                "spin_updates_per_ns": work / (wall * 1e9),
+                "offered_updates_per_ns": work / tr[-1].arrival / 1e9,
+                "scheduler": {k: (round(v, 3) if isinstance(v, float) else v)
+                              for k, v in srv.stats.items()}}
+
+    main = serve(trace)
+    capacity = main["spin_updates_per_ns"]
+    main["rho"] = main["offered_updates_per_ns"] / capacity
+    sweep = {}
+    if args.serve_load_sweep:
+        for rate, n in ((100.0, max(50, args.serve_requests // 2)),
+                        (50.0, max(25, args.serve_requests // 4))):
+            r = serve(S.poisson_trace(n=n, rate=rate, seed=2))
+            r["rho"] = r["offered_updates_per_ns"] / capacity
+            sweep[f"{int(rate)}_per_s"] = {k: v for k, v in r.items() if k != "scheduler"}
+            note(f"served at {rate:.0f}/s: p50 {r['p50_latency_s']:.3f} s, "
+                 f"p99 {r['p99_latency_s']:.3f} s, rho {r['rho']:.2f}")
+    sample = trace[::10]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     for r in sample:
@@ -433,15 +457,12 @@ def served_leg(args, torch):
     plain = sum(r.L ** 3 * r.sweeps * r.k for r in sample) / ((time.perf_counter() - t1) * 1e9)
     return {"workload": f"{len(trace)} requests, Poisson 200/s, L in {{8,16,32,64,96}}, "
                         "T in [0.1,1], sweeps log-uniform [100,1e4], k in {1,4}, binary32",
-            "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
-            "mean_latency_s": st["mean_s"], "wall_s": wall,
-            "spin_updates_per_ns": upd / (wall * 1e9),
-            "offered_updates_per_ns": offered,
+            **{k: v for k, v in main.items() if k != "scheduler"},
             "plain_per_lattice_updates_per_ns": plain,
-            "speedup_vs_plain": upd / (wall * 1e9) / plain, "budget_mb": args.serve_budget_mb,
+            "plain_sample": f"every 10th request of the trace ({len(sample)} requests)",
+            "speedup_vs_plain": capacity / plain, "budget_mb": args.serve_budget_mb,
             "step_sweeps": args.serve_step, "tile_sites": tile,
-            "scheduler": {k: (round(v, 3) if isinstance(v, float) else v)
-                          for k, v in srv.stats.items()}}
+            "load_sweep": sweep, "scheduler": main["scheduler"]}
 
 
 def cpu_model() -> str:

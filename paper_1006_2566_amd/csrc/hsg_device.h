@@ -53,6 +53,44 @@ __device__ __forceinline__ Word4 philox10(uint32_t c0, uint32_t c1, uint32_t c2,
   return Word4{c0, c1, c2, c3};
 }
 
+// NB Philox4x32-10 blocks whose counters differ only in word 2, advanced round by round
+// together: each block's arithmetic is philox10's, and the NB independent chains of
+// dependent products are interleaved in the instruction stream (latency hiding for a
+// wave that has few others beside it on its SIMD).
+template <int NB>
+__device__ __forceinline__ void philox10_n(uint32_t c0, uint32_t c1, const uint32_t (&c2)[NB],
+                                           uint32_t c3, uint32_t k0, uint32_t k1,
+                                           Word4 (&out)[NB]) {
+  uint32_t w0[NB], w1[NB], w2[NB], w3[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    w0[i] = c0;
+    w1[i] = c1;
+    w2[i] = c2[i];
+    w3[i] = c3;
+  }
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const uint64_t a = (uint64_t)w0[i] * 0xD2511F53u;
+      const uint64_t b = (uint64_t)w2[i] * 0xCD9E8D57u;
+      const uint32_t n0 = round >= 3 ? xor3_v((uint32_t)(b >> 32), w1[i], k0)
+                                     : (uint32_t)(b >> 32) ^ w1[i] ^ k0;
+      const uint32_t n2 = round >= 4 ? xor3_v((uint32_t)(a >> 32), w3[i], k1)
+                                     : (uint32_t)(a >> 32) ^ w3[i] ^ k1;
+      w1[i] = (uint32_t)b;
+      w3[i] = (uint32_t)a;
+      w0[i] = n0;
+      w2[i] = n2;
+    }
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) out[i] = Word4{w0[i], w1[i], w2[i], w3[i]};
+}
+
 // Uniform in (0,1): the top 23 bits of w as an odd multiple of 2^-24.  Exact in
 // binary32 and binary64 (the same value in both precisions).
 template <typename R>

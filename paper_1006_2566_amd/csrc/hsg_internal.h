@@ -60,7 +60,12 @@ __host__ __device__ inline Planes<R> planes_of(void* base, int64_t half_sites) {
   return out;
 }
 
-enum class PassMode : int { Metropolis = 0, OverRelax = 1, HeatBath = 2 };
+// MetropolisFull is Metropolis when k_hits is a multiple of four, so that every group of
+// four hits is complete (the launchers choose it; the arithmetic is Metropolis's).
+enum class PassMode : int { Metropolis = 0, OverRelax = 1, HeatBath = 2, MetropolisFull = 3 };
+__host__ __device__ inline PassMode metropolis_mode(int32_t k_hits) {
+  return k_hits % 4 == 0 ? PassMode::MetropolisFull : PassMode::Metropolis;
+}
 
 template <typename R>
 struct PassArgs {

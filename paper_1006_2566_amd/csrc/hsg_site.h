@@ -105,22 +105,47 @@ __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uin
     constexpr int U = 3;             // uniforms per hit
     constexpr int H = 4;             // hits per group
     constexpr int NB = U * H / 4;    // Philox blocks per group
+    // every group complete (k_hits a multiple of four): no per-group conditions
+    constexpr bool kFull = MODE == PassMode::MetropolisFull;
     R sh = dot3(s, h);
     uint32_t b0 = 0;
     for (int32_t j0 = 0; j0 < hc.k_hits; j0 += H, b0 += NB) {
       const int32_t nh = hc.k_hits - j0;  // hits left (the group takes min(H, nh))
       uint32_t w[4 * NB];
+      auto block = [&](int i) {
+        const Word4 x = philox10(hc.sweep, site, (hc.phase << 16) | (b0 + (uint32_t)i), tag,
+                                 hc.seed_lo, hc.seed_hi);
+        w[4 * i] = x.w0;
+        w[4 * i + 1] = x.w1;
+        w[4 * i + 2] = x.w2;
+        w[4 * i + 3] = x.w3;
+      };
+      if (kFull) {
+        // a full group: its NB blocks advanced together (philox10_n)
+        uint32_t c2[NB];
 #pragma unroll
-      for (int i = 0; i < NB; ++i) {
-        if (i == 0 || 4 * i < U * nh) {
-          const Word4 x = philox10(hc.sweep, site, (hc.phase << 16) | (b0 + (uint32_t)i), tag,
-                                   hc.seed_lo, hc.seed_hi);
-          w[4 * i] = x.w0;
-          w[4 * i + 1] = x.w1;
-          w[4 * i + 2] = x.w2;
-          w[4 * i + 3] = x.w3;
+        for (int i = 0; i < NB; ++i) c2[i] = (hc.phase << 16) | (b0 + (uint32_t)i);
+        Word4 x[NB];
+        philox10_n<NB>(hc.sweep, site, c2, tag, hc.seed_lo, hc.seed_hi, x);
+        // all words complete here (an empty statement that takes them as operands):
+        // without it each block's rounds would be sunk to its first use, behind the
+        // previous hit's decision, one chain at a time again
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          asm volatile("" : "+v"(x[i].w0), "+v"(x[i].w1), "+v"(x[i].w2), "+v"(x[i].w3));
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          w[4 * i] = x[i].w0;
+          w[4 * i + 1] = x[i].w1;
+          w[4 * i + 2] = x[i].w2;
+          w[4 * i + 3] = x[i].w3;
         }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i)
+          if (i == 0 || 4 * i < U * nh) block(i);
       }
+      (void)nh;
       Vec3<R> trial[H];
       R th[H], u2[H];
       auto draw = [&](int g) {
@@ -140,7 +165,7 @@ __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uin
       if constexpr (G == 1) {
 #pragma unroll
         for (int g = 0; g < H; ++g) {
-          if (g < nh) {
+          if (kFull || g < nh) {
             draw(g);
             decide(g);
           }
@@ -148,10 +173,10 @@ __device__ __forceinline__ double apply_update(Vec3<R>& s, const Vec3<R>& h, uin
       } else {
 #pragma unroll
         for (int g = 0; g < H; ++g)
-          if (g < nh) draw(g);
+          if (kFull || g < nh) draw(g);
 #pragma unroll
         for (int g = 0; g < H; ++g)
-          if (g < nh) decide(g);
+          if (kFull || g < nh) decide(g);
       }
     }
   }
@@ -210,6 +235,70 @@ __device__ __forceinline__ double update_site(const Planes<R>& S, const Planes<R
   S.p[oc + 0][own] = s.x;
   S.p[oc + 1][own] = s.y;
   S.p[oc + 2][own] = s.z;
+  return dE_sum;
+}
+
+// Element at byte offset `off` of a plane whose base is wave-uniform: the access uses
+// the scalar-base + 32-bit vector-offset addressing of global loads and stores, with no
+// 64-bit address arithmetic per lane.  A binary32 plane of N/2 <= 2^30 values spans less
+// than 2^32 bytes for every L the library accepts.
+__device__ __forceinline__ float plane_ld(const float* base, uint32_t off) {
+  return *(const float*)((const char*)base + off);
+}
+// The same for data the pass only reads; with NT the load carries the non-temporal hint.
+template <bool NT>
+__device__ __forceinline__ float plane_ld_ro(const float* base, uint32_t off) {
+  const float* p = (const float*)((const char*)base + off);
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+__device__ __forceinline__ void plane_st(float* base, uint32_t off, float v) {
+  *(float*)((char*)base + off) = v;
+}
+
+// The binary32 site update of the colour passes (single lattice, batched, served): the same field (eq. 2, same
+// order of products and fused multiply-adds) and the same apply_update as update_site,
+// with 32-bit byte offsets into the six planes.
+template <PassMode MODE, bool NT>
+__device__ __forceinline__ double update_site_b32(const Planes<float>& S, const Planes<float>& J,
+                                                  const SitePos& q, const HitCtx<float>& hc) {
+  const uint32_t L = (uint32_t)q.L, Lh = (uint32_t)q.Lh, xh = (uint32_t)q.xh;
+  const uint32_t y = (uint32_t)q.y, z = (uint32_t)q.z;
+  const int32_t c = q.c;
+  const uint32_t p = (y + z + (uint32_t)c) & 1u;  // x = 2 xh + p
+  const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
+  const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
+  const uint32_t row = Lh * (y + L * z);
+  const uint32_t own = (row + xh) << 2;
+  const uint32_t n_px = (row + (p ? (xh + 1 == Lh ? 0 : xh + 1) : xh)) << 2;
+  const uint32_t n_mx = (row + (p ? xh : (xh == 0 ? Lh - 1 : xh - 1))) << 2;
+  const uint32_t n_py = (Lh * (yp + L * z) + xh) << 2, n_my = (Lh * (ym + L * z) + xh) << 2;
+  const uint32_t n_pz = (Lh * (y + L * zp) + xh) << 2, n_mz = (Lh * (y + L * zm) + xh) << 2;
+  const int oc = 3 * c, nc = 3 * (1 - c);
+  const float j_px = plane_ld_ro<NT>(J.p[oc + 0], own), j_mx = plane_ld_ro<NT>(J.p[nc + 0], n_mx);
+  const float j_py = plane_ld_ro<NT>(J.p[oc + 1], own), j_my = plane_ld_ro<NT>(J.p[nc + 1], n_my);
+  const float j_pz = plane_ld_ro<NT>(J.p[oc + 2], own), j_mz = plane_ld_ro<NT>(J.p[nc + 2], n_mz);
+  float hcomp[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const float* sn = S.p[nc + k];
+    float acc = j_px * plane_ld_ro<NT>(sn, n_px);
+    acc = dev_fma(j_mx, plane_ld_ro<NT>(sn, n_mx), acc);
+    acc = dev_fma(j_py, plane_ld_ro<NT>(sn, n_py), acc);
+    acc = dev_fma(j_my, plane_ld_ro<NT>(sn, n_my), acc);
+    acc = dev_fma(j_pz, plane_ld_ro<NT>(sn, n_pz), acc);
+    acc = dev_fma(j_mz, plane_ld_ro<NT>(sn, n_mz), acc);
+    hcomp[k] = acc;
+  }
+  const Vec3<float> h{hcomp[0], hcomp[1], hcomp[2]};
+  Vec3<float> s{plane_ld(S.p[oc + 0], own), plane_ld(S.p[oc + 1], own), plane_ld(S.p[oc + 2], own)};
+  const uint32_t site = (2 * xh + p) + L * (y + L * z);
+  const double dE_sum = apply_update<float, MODE>(s, h, site, hc);
+  plane_st(S.p[oc + 0], own, s.x);
+  plane_st(S.p[oc + 1], own, s.y);
+  plane_st(S.p[oc + 2], own, s.z);
   return dE_sum;
 }
 

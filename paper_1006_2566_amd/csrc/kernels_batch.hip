@@ -67,6 +67,17 @@ struct BatchArgs {
   int32_t n_sweeps;
 };
 
+// The site update of a chain's site: the binary32 form (scalar plane bases, 32-bit
+// offsets) or the generic one.
+template <typename R, PassMode MODE>
+__device__ __forceinline__ double site_update(const ChainView<R>& v, const SitePos& q,
+                                              const HitCtx<R>& hc) {
+  if constexpr (sizeof(R) == 4)
+    return update_site_b32<MODE, false>(v.S, v.J, q, hc);
+  else
+    return update_site<R, MODE>(v.S, v.J, q, hc);
+}
+
 // One colour pass of mode MODE over a chain, spread over the workgroup.  The colour
 // is a compile-time constant, so the site update addresses its planes with constant
 // indices (no pointer table in scratch memory, global rather than flat loads).
@@ -84,7 +95,10 @@ __device__ __forceinline__ double chain_pass(const ChainView<R>& v, const HitCtx
     const uint32_t zq = by_l.div(r);
     q.y = (int32_t)(r - zq * (uint32_t)v.L);
     q.z = (int32_t)zq;
-    dE += update_site<R, MODE>(v.S, v.J, q, hc);
+    if constexpr (sizeof(R) == 4)
+      dE += update_site_b32<MODE, false>(v.S, v.J, q, hc);
+    else
+      dE += update_site<R, MODE>(v.S, v.J, q, hc);
   }
   return dE;
 }
@@ -151,6 +165,10 @@ __global__ __launch_bounds__(1024) void batch_sweep_kernel(BatchArgs<R> a) {
         dE += chain_pass<R, PassMode::HeatBath, 0>(v, hc, by_lh, by_l);
         __syncthreads();
         dE += chain_pass<R, PassMode::HeatBath, 1>(v, hc, by_lh, by_l);
+      } else if (ch.k_hits % 4 == 0) {  // every group of four hits complete
+        dE += chain_pass<R, PassMode::MetropolisFull, 0>(v, hc, by_lh, by_l);
+        __syncthreads();
+        dE += chain_pass<R, PassMode::MetropolisFull, 1>(v, hc, by_lh, by_l);
       } else {
         dE += chain_pass<R, PassMode::Metropolis, 0>(v, hc, by_lh, by_l);
         __syncthreads();
@@ -327,11 +345,13 @@ __global__ __launch_bounds__(1024) void multi_pass_kernel(MultiPassArgs<R> a) {
     q.y = (int32_t)(r - zq * (uint32_t)v.L);
     q.z = (int32_t)zq;
     if (a.phase > 0)
-      update_site<R, PassMode::OverRelax>(v.S, v.J, q, hc);
+      site_update<R, PassMode::OverRelax>(v, q, hc);
     else if (ch.flags & HSG_HEAT_BATH)
-      dE = update_site<R, PassMode::HeatBath>(v.S, v.J, q, hc);
+      dE = site_update<R, PassMode::HeatBath>(v, q, hc);
+    else if (ch.k_hits % 4 == 0)  // every group of four hits complete
+      dE = site_update<R, PassMode::MetropolisFull>(v, q, hc);
     else
-      dE = update_site<R, PassMode::Metropolis>(v.S, v.J, q, hc);
+      dE = site_update<R, PassMode::Metropolis>(v, q, hc);
   }
   if (a.phase == 0) {
     const double total = block_sum(dE, s_red);

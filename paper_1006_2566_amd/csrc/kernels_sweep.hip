@@ -49,70 +49,6 @@ size_t work_bytes_for(int32_t L, int32_t dtype_bytes) {
   return fused_offset(L) + (size_t)3 * L * L * L * (size_t)dtype_bytes;
 }
 
-// Element at byte offset `off` of a plane whose base is wave-uniform: the access uses
-// the scalar-base + 32-bit vector-offset addressing of global loads and stores, with no
-// 64-bit address arithmetic per lane.  A binary32 plane of N/2 <= 2^30 values spans less
-// than 2^32 bytes for every L the library accepts.
-__device__ __forceinline__ float plane_ld(const float* base, uint32_t off) {
-  return *(const float*)((const char*)base + off);
-}
-// The same for data the pass only reads; with NT the load carries the non-temporal hint.
-template <bool NT>
-__device__ __forceinline__ float plane_ld_ro(const float* base, uint32_t off) {
-  const float* p = (const float*)((const char*)base + off);
-  if constexpr (NT)
-    return __builtin_nontemporal_load(p);
-  else
-    return *p;
-}
-__device__ __forceinline__ void plane_st(float* base, uint32_t off, float v) {
-  *(float*)((char*)base + off) = v;
-}
-
-// The binary32 site update of the single-lattice pass: the same field (eq. 2, same
-// order of products and fused multiply-adds) and the same apply_update as update_site,
-// with 32-bit byte offsets into the six planes.
-template <PassMode MODE, bool NT>
-__device__ __forceinline__ double update_site_b32(const Planes<float>& S, const Planes<float>& J,
-                                                  const SitePos& q, const HitCtx<float>& hc) {
-  const uint32_t L = (uint32_t)q.L, Lh = (uint32_t)q.Lh, xh = (uint32_t)q.xh;
-  const uint32_t y = (uint32_t)q.y, z = (uint32_t)q.z;
-  const int32_t c = q.c;
-  const uint32_t p = (y + z + (uint32_t)c) & 1u;  // x = 2 xh + p
-  const uint32_t ym = y == 0 ? L - 1 : y - 1, yp = y == L - 1 ? 0 : y + 1;
-  const uint32_t zm = z == 0 ? L - 1 : z - 1, zp = z == L - 1 ? 0 : z + 1;
-  const uint32_t row = Lh * (y + L * z);
-  const uint32_t own = (row + xh) << 2;
-  const uint32_t n_px = (row + (p ? (xh + 1 == Lh ? 0 : xh + 1) : xh)) << 2;
-  const uint32_t n_mx = (row + (p ? xh : (xh == 0 ? Lh - 1 : xh - 1))) << 2;
-  const uint32_t n_py = (Lh * (yp + L * z) + xh) << 2, n_my = (Lh * (ym + L * z) + xh) << 2;
-  const uint32_t n_pz = (Lh * (y + L * zp) + xh) << 2, n_mz = (Lh * (y + L * zm) + xh) << 2;
-  const int oc = 3 * c, nc = 3 * (1 - c);
-  const float j_px = plane_ld_ro<NT>(J.p[oc + 0], own), j_mx = plane_ld_ro<NT>(J.p[nc + 0], n_mx);
-  const float j_py = plane_ld_ro<NT>(J.p[oc + 1], own), j_my = plane_ld_ro<NT>(J.p[nc + 1], n_my);
-  const float j_pz = plane_ld_ro<NT>(J.p[oc + 2], own), j_mz = plane_ld_ro<NT>(J.p[nc + 2], n_mz);
-  float hcomp[3];
-#pragma unroll
-  for (int k = 0; k < 3; ++k) {
-    const float* sn = S.p[nc + k];
-    float acc = j_px * plane_ld_ro<NT>(sn, n_px);
-    acc = dev_fma(j_mx, plane_ld_ro<NT>(sn, n_mx), acc);
-    acc = dev_fma(j_py, plane_ld_ro<NT>(sn, n_py), acc);
-    acc = dev_fma(j_my, plane_ld_ro<NT>(sn, n_my), acc);
-    acc = dev_fma(j_pz, plane_ld_ro<NT>(sn, n_pz), acc);
-    acc = dev_fma(j_mz, plane_ld_ro<NT>(sn, n_mz), acc);
-    hcomp[k] = acc;
-  }
-  const Vec3<float> h{hcomp[0], hcomp[1], hcomp[2]};
-  Vec3<float> s{plane_ld(S.p[oc + 0], own), plane_ld(S.p[oc + 1], own), plane_ld(S.p[oc + 2], own)};
-  const uint32_t site = (2 * xh + p) + L * (y + L * z);
-  const double dE_sum = apply_update<float, MODE>(s, h, site, hc);
-  plane_st(S.p[oc + 0], own, s.x);
-  plane_st(S.p[oc + 1], own, s.y);
-  plane_st(S.p[oc + 2], own, s.z);
-  return dE_sum;
-}
-
 // One tile of a colour pass (a BX x BY x BZ block of the colour's sites); Metropolis
 // and heat-bath passes add the tile's accepted energy changes to partials[tile] in a
 // fixed order (wave sums, then the waves in order).  `tile` must be wave-uniform.
@@ -165,8 +101,13 @@ void launch_pass_kind(PassMode mode, const PassArgs<R>& a, hipStream_t stream) {
   const dim3 grid((unsigned)a.tile_count), block(256);
   switch (mode) {
     case PassMode::Metropolis:
-      hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis, NT>), grid, block, 0, stream,
-                         a);
+    case PassMode::MetropolisFull:
+      if (metropolis_mode(a.k_hits) == PassMode::MetropolisFull)
+        hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::MetropolisFull, NT>), grid, block, 0,
+                           stream, a);
+      else
+        hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::Metropolis, NT>), grid, block, 0,
+                           stream, a);
       break;
     case PassMode::OverRelax:
       hipLaunchKernelGGL((colour_pass_kernel<R, PassMode::OverRelax, NT>), grid, block, 0, stream,
