@@ -151,6 +151,23 @@ int hsg_export(const hsg_lattice *lat, void *canon_spins, void *canon_J, void *s
  * the sweep index would pass 2^32. */
 int hsg_sweep(hsg_lattice *lat, const hsg_sweep_params *p, int32_t n_sweeps, void *stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation -- and so cannot provide a work buffer:
+ * hsg_sweep with the same arguments and results, lat->work and lat->work_bytes ignored.
+ * Its scratch (the per-tile energy partials) is a fixed array inside the library,
+ * HSG_NOALLOC_SCRATCH_BYTES on every GPU the library runs on, held until the process
+ * ends; the call allocates nothing and calls no allocating routine.  Limits: L <=
+ * HSG_NOALLOC_L_MAX, and the pass-by-pass schedule only (HSG_SNAKE, HSG_PLANE_LAUNCH,
+ * HSG_STREAM_LOADS, HSG_HEAT_BATH honoured; HSG_FUSED, HSG_MARCH_PHASE, HSG_PHASE_LAUNCH
+ * and HSG_PHASE_MC, which need a second spin array, give HSG_EINVAL), as does any larger
+ * L.  Every call on one GPU shares that GPU's array (cleared at the start of each call):
+ * calls that overlap on one GPU -- on different streams, or from different threads --
+ * race and must be ordered by the caller. */
+#define HSG_NOALLOC_L_MAX 512
+#define HSG_NOALLOC_SCRATCH_BYTES (2u << 20) /* 262144 partials: L = 512 */
+int hsg_sweep_noalloc(hsg_lattice *lat, const hsg_sweep_params *p, int32_t n_sweeps,
+                      void *stream);
+
 /* Kinds of launch reported by hsg_sweep_timed. */
 #define HSG_LAUNCH_OTHER 0        /* renormalisation, energy fold */
 #define HSG_LAUNCH_MC_PASS 1      /* Metropolis or heat-bath colour pass */

@@ -104,12 +104,14 @@ def lib() -> ctypes.CDLL:
         L.hsg_sweep.argtypes = [LP, ctypes.POINTER(_SweepParams), I32, P]
         L.hsg_sweep_timed.argtypes = [LP, ctypes.POINTER(_SweepParams), I32, P, I32, P, P,
                                       ctypes.POINTER(I32)]
+        L.hsg_sweep_noalloc.argtypes = [LP, ctypes.POINTER(_SweepParams), I32, P]
         L.hsg_energy.argtypes = [LP, I32, P, P]
         L.hsg_overlap.argtypes = [LP, LP, P, P]
         L.hsg_overlap_fourier.argtypes = [LP, LP, P, P]
         L.hsg_last_error.restype = ctypes.c_char_p
         for name in ("hsg_lattice_bytes", "hsg_init_lattice", "hsg_import", "hsg_export",
-                     "hsg_sweep", "hsg_sweep_timed", "hsg_energy", "hsg_overlap",
+                     "hsg_sweep", "hsg_sweep_timed", "hsg_sweep_noalloc", "hsg_energy",
+                     "hsg_overlap",
                      "hsg_overlap_fourier"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L

@@ -6,6 +6,7 @@
 #include <stdio.h>
 
 #include <algorithm>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -128,15 +129,17 @@ bool renorm_due(const hsg_sweep_params* p, uint64_t sweep) {
 // pass of the next sweep of the call (and the renormalisation between them when due);
 // that sweep then starts with its colour-1 pass.
 template <typename R>
-int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
+int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st,
+                double* partials) {
   using namespace hsg;
   const Geometry g = pass_geometry(lat->L);
   const int64_t Nh = (int64_t)lat->L * lat->L * lat->L / 2;
   PassArgs<R> a{};
-  R* bufs[2] = {(R*)lat->spins, (R*)((char*)lat->work + fused_offset(lat->L))};
-  int cur = 0;  // buffer holding the current spins (phase launches flip it)
   const bool phase_launch =
       (p->flags & (HSG_PHASE_LAUNCH | HSG_PHASE_MC)) && phase_supported(lat->L);
+  R* bufs[2] = {(R*)lat->spins,
+                phase_launch ? (R*)((char*)lat->work + fused_offset(lat->L)) : nullptr};
+  int cur = 0;  // buffer holding the current spins (phase launches flip it)
   const bool phase_mc = phase_launch && (p->flags & HSG_PHASE_MC) && p->k_hits > 0;
   // an odd count of phase launches: the call's last phase runs as colour passes
   const bool last_as_passes =
@@ -150,7 +153,7 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   ph.L = lat->L;
   a.spins = planes_of<R>(bufs[cur], Nh);
   a.J = planes_of<R>(lat->J, Nh);
-  a.partials = pass_partials(lat->work);
+  a.partials = partials;
   a.beta = (R)(1.0 / p->T);
   a.seed_lo = (uint32_t)lat->seed;
   a.seed_hi = (uint32_t)(lat->seed >> 32);
@@ -159,7 +162,7 @@ int sweep_plain(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, h
   a.nt = (p->flags & HSG_STREAM_LOADS) ? 1 : 0;
   const PassMode mc = (p->flags & HSG_HEAT_BATH) ? PassMode::HeatBath : PassMode::Metropolis;
   ph.mc_mode = (int32_t)mc;
-  ph.partials = pass_partials(lat->work);
+  ph.partials = partials;
   const bool snake = (p->flags & HSG_SNAKE) != 0;
   const bool by_slab = (p->flags & HSG_PLANE_LAUNCH) != 0;
   const int32_t slab_tiles = g.tiles_x * g.tiles_y;
@@ -308,16 +311,19 @@ bool use_fused(const hsg_lattice* lat, const hsg_sweep_params* p) {
   return (p->flags & HSG_FUSED) && hsg::march_supported(lat->L);
 }
 
+// partials: the per-tile energy-change partials (pass_geometry(L).n_blocks doubles, zero
+// on entry and zeroed again by the fold).
 template <typename R>
-int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st) {
+int sweep_impl(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps, hipStream_t st,
+               double* partials) {
   using namespace hsg;
   int rc = use_fused(lat, p) ? sweep_fused<R>(lat, p, n_sweeps, st)
-                             : sweep_plain<R>(lat, p, n_sweeps, st);
+                             : sweep_plain<R>(lat, p, n_sweeps, st, partials);
   if (rc) return rc;
   if (n_sweeps > 0 && p->k_hits > 0) {
     rc = device_status(recorded(HSG_LAUNCH_OTHER, st,
                                 [&] {
-                                  return launch_fold_partials(pass_partials(lat->work),
+                                  return launch_fold_partials(partials,
                                                               pass_geometry(lat->L).n_blocks,
                                                               lat->E, st);
                                 }),
@@ -450,8 +456,83 @@ static int sweep_checked(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_
                             "(has %zu)",
                 hsg::work_bytes_for(lat->L, (int32_t)elem), lat->work_bytes);
   hipStream_t st = as_stream(stream);
-  rc = lat->dtype == HSG_F32 ? sweep_impl<float>(lat, p, n_sweeps, st)
-                             : sweep_impl<double>(lat, p, n_sweeps, st);
+  double* partials = hsg::pass_partials(lat->work);
+  rc = lat->dtype == HSG_F32 ? sweep_impl<float>(lat, p, n_sweeps, st, partials)
+                             : sweep_impl<double>(lat, p, n_sweeps, st, partials);
+  if (rc == HSG_OK) lat->sweep += (uint64_t)n_sweeps;
+  return rc;
+}
+
+/* ---------------------------------------------------- sweeps without a work buffer */
+
+// The library's own scratch for hsg_sweep_noalloc: the per-tile energy partials of the
+// pass-by-pass schedule for lattices up to HSG_NOALLOC_L_MAX, one copy per GPU (the array
+// lives in every device's copy of the code object until the process ends).  Host code
+// uses the device address hipGetSymbolAddress returns for the current device, never the
+// array's name.
+constexpr size_t kNoAllocPartials = HSG_NOALLOC_SCRATCH_BYTES / sizeof(double);
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double* g_scratch_ptr[kMaxDevices];
+
+// The current device's address of `scratch` (looked up once per device).
+static int scratch_for_current_device(double** out) {
+  int dev = -1;
+  int rc = device_status(hipGetDevice(&dev), "hipGetDevice");
+  if (rc) return rc;
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(HSG_EUNSUPPORTED, "hsg_sweep_noalloc: device %d beyond the first %d", dev,
+                kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    rc = device_status(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+    if (rc) return rc;
+    if (!ptr) return fail(HSG_EDEVICE, "hipGetSymbolAddress returned NULL for the scratch array");
+    g_scratch_ptr[dev] = (double*)ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HSG_OK;
+}
+
+int hsg_sweep_noalloc(hsg_lattice* lat, const hsg_sweep_params* p, int32_t n_sweeps,
+                      void* stream) {
+  if (!lat) return fail(HSG_EINVAL, "lattice descriptor is NULL");
+  int rc = check_dims(lat->L, lat->dtype);
+  if (rc) return rc;
+  if (!lat->spins || !lat->J || !lat->E)
+    return fail(HSG_EINVAL, "lattice buffers spins, J and E must be set");
+  if (lat->L > HSG_NOALLOC_L_MAX)
+    return fail(HSG_EINVAL, "hsg_sweep_noalloc: L = %d beyond HSG_NOALLOC_L_MAX = %d", (int)lat->L,
+                HSG_NOALLOC_L_MAX);
+  rc = check_params(p);
+  if (rc) return rc;
+  if (p->flags & (HSG_FUSED | HSG_MARCH_PHASE | HSG_PHASE_LAUNCH | HSG_PHASE_MC))
+    return fail(HSG_EINVAL, "hsg_sweep_noalloc runs the pass-by-pass schedule: HSG_FUSED, "
+                            "HSG_MARCH_PHASE, HSG_PHASE_LAUNCH and HSG_PHASE_MC need a second "
+                            "spin array");
+  if (n_sweeps < 0) return fail(HSG_EINVAL, "n_sweeps must be >= 0");
+  if (lat->sweep + (uint64_t)n_sweeps > 0x100000000ull)
+    return fail(HSG_EINVAL, "sweep index would pass 2^32");
+  const int32_t n_blocks = hsg::pass_geometry(lat->L).n_blocks;
+  if ((size_t)n_blocks > kNoAllocPartials)
+    return fail(HSG_EINVAL, "hsg_sweep_noalloc: %d partials exceed the scratch array",
+                (int)n_blocks);
+  double* partials = nullptr;
+  rc = scratch_for_current_device(&partials);
+  if (rc) return rc;
+  hipStream_t st = as_stream(stream);
+  // the array keeps the last call's contents: the partials must start at zero (a fill
+  // kernel, not a memset node, so the call can be captured in a graph)
+  rc = device_status(hsg::launch_zero(partials, n_blocks, st), "clear scratch");
+  if (rc) return rc;
+  hsg_lattice view = *lat;  // the pass-by-pass schedule never touches work
+  view.work = nullptr;
+  view.work_bytes = 0;
+  rc = lat->dtype == HSG_F32 ? sweep_impl<float>(&view, p, n_sweeps, st, partials)
+                             : sweep_impl<double>(&view, p, n_sweeps, st, partials);
   if (rc == HSG_OK) lat->sweep += (uint64_t)n_sweeps;
   return rc;
 }

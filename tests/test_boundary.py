@@ -273,3 +273,27 @@ def test_sweep_timed_rejects_bad_outputs(hsg):
                                ctypes.byref(n)) == -1
     assert b"T must be" in lib.hsg_last_error()
     assert n.value == 0  # nothing was recorded
+
+
+def test_noalloc_sweep_rejects_what_needs_scratch_it_does_not_have(hsg):
+    """hsg_sweep_noalloc checks its limits before anything reaches the device: L beyond
+    its scratch, traversals that need a second spin array, and the usual arguments; it
+    needs no work buffer."""
+    lib = hsg.lib()
+    lib.hsg_sweep_noalloc.argtypes = [ctypes.POINTER(hsg._Lattice),
+                                      ctypes.POINTER(hsg._SweepParams), ctypes.c_int32,
+                                      ctypes.c_void_p]
+    p = hsg._SweepParams(1.0, 1, 1, 0, 0)
+    big = hsg._Lattice(514, 0, 1, 0, 0x1000, 0x2000, 0x3000, None, 0)
+    assert lib.hsg_sweep_noalloc(ctypes.byref(big), ctypes.byref(p), 1, None) == -1
+    assert b"HSG_NOALLOC_L_MAX" in lib.hsg_last_error()
+    d = hsg._Lattice(64, 0, 1, 0, 0x1000, 0x2000, 0x3000, None, 0)
+    for flag in (hsg.HSG_FUSED, hsg.HSG_PHASE_LAUNCH, hsg.HSG_PHASE_MC):
+        q = hsg._SweepParams(1.0, 1, 1, 0, flag)
+        assert lib.hsg_sweep_noalloc(ctypes.byref(d), ctypes.byref(q), 1, None) == -1
+        assert b"second" in lib.hsg_last_error() or b"HSG_FUSED" in lib.hsg_last_error()
+    bad = hsg._SweepParams(0.0, 1, 1, 0, 0)
+    assert lib.hsg_sweep_noalloc(ctypes.byref(d), ctypes.byref(bad), 1, None) == -1
+    nospins = hsg._Lattice(64, 0, 1, 0, None, 0x2000, 0x3000, None, 0)
+    assert lib.hsg_sweep_noalloc(ctypes.byref(nospins), ctypes.byref(p), 1, None) == -1
+    assert lib.hsg_sweep_noalloc(None, ctypes.byref(p), 1, None) == -1
