@@ -467,149 +467,6 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
   }
 }
 
-// ----------------------------------------------------------------------------------------
-// The phase with the next colour-0 Monte Carlo pass, split by wave: in a workgroup of
-// 1024 threads, waves 0-7 run the Monte Carlo stage (C) and waves 8-15 the two
-// over-relaxation stages (A, B), with the stages two planes apart:
-//
-//   step t, q = z0 - 2 + t:   A  colour 0, over-relaxation, ring 2, plane q
-//                             B  colour 1, over-relaxation, ring 1, plane q - 2
-//                             C  colour 0, Monte Carlo, the tile, plane q - 4
-//
-// A writes colour 0 on q and reads colour 1 on q-1..q+1, which B has not reached; B
-// writes colour 1 on q-2 and reads colour 0 on q-3..q-1, which A finished in earlier steps
-// and C has not reached; C writes colour 0 on q-4 and reads colour 1 on q-5..q-3, which B
-// finished in earlier steps.  So the three stages of a step touch no common value and
-// run side by side: the memory-latency-bound over-relaxation waves and the issue-bound
-// Monte Carlo waves share each compute unit, with one barrier per step.  The window holds
-// colour 0 on q-4..q and colour 1 on q-5..q+1, plus one slot of each colour for the plane
-// the next step needs (put during this step into a slot no stage of this step touches):
-// 6 + 8 slices, 133 KB, one workgroup per compute unit.  Each stage's couplings are
-// fetched one step ahead into registers.  Results equal the three-stage march's (and the
-// pass-by-pass schedule's) bit for bit: every site sees the same neighbour values and
-// runs the same arithmetic.
-constexpr int kSplitThreads = 1024;
-constexpr int kSplitHalf = 512;  // the Monte Carlo waves: one tile site per thread
-using WinSplit = Win<3, 6, 8, kSplitThreads>;
-constexpr int kSplitSteps = kPZ + 6;
-constexpr bool kSplitEnabled = false;
-static_assert(StageShape<WinSplit, 0>::COUNT == kSplitHalf, "stage C: one tile site per thread");
-// The over-relaxation waves take the items of stage A (ring 2), then those of stage B
-// (ring 1): item j of a step, j = thread + 512 r, is site j of A if j < A_COUNT, else site
-// j - A_COUNT of B.
-constexpr int kSplitA = StageShape<WinSplit, 2>::COUNT;
-constexpr int kSplitB = StageShape<WinSplit, 1>::COUNT;
-constexpr int kSplitRounds = (kSplitA + kSplitB + kSplitHalf - 1) / kSplitHalf;
-
-template <typename R, PassMode MC>
-__global__ __launch_bounds__(kSplitThreads) void phase_split_kernel(PhaseArgs<R> a) {
-  using W = WinSplit;
-  constexpr PassMode OR = PassMode::OverRelax;
-  __shared__ R lds[(W::K0 + W::K1) * W::SLICE];
-  const PhaseCtx m = phase_ctx(a.L, kPZ);
-  const HitCtx<R> hc{a.beta, a.sweep, a.phase, a.k_hits, a.seed_lo, a.seed_hi};
-  const HitCtx<R> hm{a.beta, a.mc_sweep, 0u, a.k_hits, a.seed_lo, a.seed_hi};
-  const bool rn = a.renorm != 0;
-  const bool mc_wave = threadIdx.x < kSplitHalf;  // wave-uniform: waves 0-7
-  const int32_t u = (int32_t)threadIdx.x - (mc_wave ? 0 : kSplitHalf);
-  SliceOffsets<W> so;
-  slice_offsets<W>(so, m);
-  SliceRegs<R, W> r0, r1;
-  const int32_t q0 = m.z0 - 2;
-  // before step 0: colour 1 on q0-1..q0+1 and colour 0 on q0 in the window; in registers
-  // colour 0 on q0+1 and colour 1 on q0+2, put during step 0
-  for (int32_t q = q0 - 1; q <= q0 + 1; ++q) {
-    fetch<R, W>(r1, so, a.in, m, 1, q);
-    put<R, W>(lds, r1, 1, q);
-  }
-  fetch<R, W>(r0, so, a.in, m, 0, q0);
-  put<R, W>(lds, r0, 0, q0);
-  fetch<R, W>(r0, so, a.in, m, 0, q0 + 1);
-  fetch<R, W>(r1, so, a.in, m, 1, q0 + 2);
-
-  // couplings one step ahead: stage C's site (Monte Carlo waves), the items of stages A
-  // and B (over-relaxation waves; item r of this thread is a site of A or of B).  Each is
-  // replaced by the next step's right after its use.
-  Bonds<R> jb[kSplitRounds];
-  auto fetch_c = [&](int32_t q) {  // stage C's site when the march reaches plane q
-    if (q - 4 >= m.z0 && q - 4 < m.z0 + kPZ)
-      jb[0] = site_bonds<R, 0>(a.J, m, site_ref<W, 0, 0>(m, q - 4, u));
-  };
-  auto fetch_item = [&](int r, int32_t q) {
-    const int32_t j = u + r * kSplitHalf;
-    if (j < kSplitA) {
-      if (q <= m.z0 + kPZ + 1) jb[r] = site_bonds<R, 0>(a.J, m, site_ref<W, 0, 2>(m, q, j));
-    } else if (j < kSplitA + kSplitB) {
-      if (q - 2 >= m.z0 - 1 && q - 2 <= m.z0 + kPZ)
-        jb[r] = site_bonds<R, 1>(a.J, m, site_ref<W, 1, 1>(m, q - 2, j - kSplitA));
-    }
-  };
-  if (mc_wave) {
-    fetch_c(q0);
-  } else {
-#pragma unroll
-    for (int r = 0; r < kSplitRounds; ++r) fetch_item(r, q0);
-  }
-  // the over-relaxation waves issue first when both kinds are ready
-  if (!mc_wave) __builtin_amdgcn_s_setprio(3);
-
-  double dE = 0.0;
-  for (int32_t t = 0; t < kSplitSteps; ++t) {
-    const int32_t q = q0 + t;
-    const bool more = t + 1 < kSplitSteps;
-    __syncthreads();
-    if (mc_wave) {
-      const Bonds<R> cur = jb[0];
-      if (more) fetch_c(q + 1);
-      if (q - 4 >= m.z0 && q - 4 < m.z0 + kPZ) {
-        const SiteRef ref = site_ref<W, 0, 0>(m, q - 4, u);
-        dE += phase_site<R, W, 0, MC, 1>(lds, a.out, m, q - 4, ref, cur, hm, rn, false, false,
-                                         true);
-      }
-    } else {
-#pragma unroll
-      for (int r = 0; r < kSplitRounds; ++r) {
-        const int32_t j = u + r * kSplitHalf;
-        const Bonds<R> cur = jb[r];
-        if (more) fetch_item(r, q + 1);
-        if (j < kSplitA) {
-          if (q <= m.z0 + kPZ + 1) {
-            const SiteRef ref = site_ref<W, 0, 2>(m, q, j);
-            phase_site<R, W, 0, OR, 1>(lds, a.out, m, q, ref, cur, hc, false, false, true, false);
-          }
-        } else if (j < kSplitA + kSplitB) {
-          if (q - 2 >= m.z0 - 1 && q - 2 <= m.z0 + kPZ) {
-            const SiteRef ref = site_ref<W, 1, 1>(m, q - 2, j - kSplitA);
-            const bool own = q - 2 >= m.z0 && q - 2 < m.z0 + kPZ;
-            phase_site<R, W, 1, OR, 1>(lds, a.out, m, q - 2, ref, cur, hc, false, rn, true, own);
-          }
-        }
-      }
-    }
-    // the planes of the next step go into the slots of colour 0 on q - 5 and colour 1 on
-    // q - 6, which no stage of this step touches
-    if (more) {
-      put<R, W>(lds, r0, 0, q + 1);
-      put<R, W>(lds, r1, 1, q + 2);
-      if (t + 2 < kSplitSteps) {
-        fetch<R, W>(r0, so, a.in, m, 0, q + 2);
-        fetch<R, W>(r1, so, a.in, m, 1, q + 3);
-      }
-    }
-  }
-  __builtin_amdgcn_s_setprio(0);
-  __shared__ double s_red[16];
-  const double total = block_sum(dE, s_red);
-  if (threadIdx.x == 0) a.partials[blockIdx.x] += total;
-}
-
-template <typename R, PassMode MC>
-hipError_t launch_split(const PhaseArgs<R>& a, hipStream_t st) {
-  const dim3 grid((unsigned)phase_blocks(a.L)), block(kSplitThreads);
-  hipLaunchKernelGGL((phase_split_kernel<R, MC>), grid, block, 0, st, a);
-  return hipGetLastError();
-}
-
 template <typename R, int NS, PassMode MC>
 hipError_t launch_ns(const PhaseArgs<R>& a, hipStream_t st) {
   const dim3 grid((unsigned)phase_blocks(a.L)), block(kPhaseThreads);
@@ -634,15 +491,6 @@ hipError_t launch_phase(const PhaseArgs<R>& a, hipStream_t st) {
   const PassMode mc = (PassMode)a.mc_mode == PassMode::HeatBath ? PassMode::HeatBath
                        : metropolis_mode(a.k_hits);
   if ((PassMode)a.mc_mode == PassMode::OverRelax) return hipErrorInvalidValue;
-  // binary32: the split launch (one workgroup of 1024 threads per compute unit); binary64
-  // keeps the three-stage march (its window would not fit the split launch's 14 slices)
-  if constexpr (sizeof(R) == 4) {
-    if (kSplitEnabled) {
-      if (mc == PassMode::MetropolisFull) return launch_split<R, PassMode::MetropolisFull>(a, st);
-      if (mc == PassMode::Metropolis) return launch_split<R, PassMode::Metropolis>(a, st);
-      return launch_split<R, PassMode::HeatBath>(a, st);
-    }
-  }
   if (mc == PassMode::MetropolisFull) return launch_ns<R, 3, PassMode::MetropolisFull>(a, st);
   if (mc == PassMode::Metropolis) return launch_ns<R, 3, PassMode::Metropolis>(a, st);
   return launch_ns<R, 3, PassMode::HeatBath>(a, st);
