@@ -111,7 +111,7 @@ def parse():
                          "(calibrates FETCH_SIZE / WRITE_SIZE), then 4 sweeps of the headline "
                          "configuration; prints no JSON")
     ap.add_argument("--reduce-counters", nargs="+", metavar="CSV",
-                    help="FETCH_CSV WRITE_CSV [ISSUE_CSV [TRACE_CSV]]: turn the "
+                    help="FETCH_CSV WRITE_CSV [ISSUE_CSV[,ISSUE_CSV...] [TRACE_CSV]]: turn the "
                          "counter_collection.csv files of a FETCH_SIZE and a WRITE_SIZE run of "
                          "--counters (and optionally of an SQ_INSTS_VALU + GRBM_GUI_ACTIVE run "
                          "and the kernel_trace.csv of a --kernel-trace run of the same command) "
@@ -166,8 +166,12 @@ def reduce_counters(fetch_csv, write_csv, issue_csv=None, trace_csv=None):
     compute unit and cycle (SQ_INSTS_VALU / (256 x GRBM_GUI_ACTIVE / 8 XCDs)); with
     trace_csv, its mean kernel-trace duration."""
     fetch, write = read_counter_csv(fetch_csv), read_counter_csv(write_csv)
-    issue = {c: read_counter_csv(issue_csv, c) for c in ("SQ_INSTS_VALU", "GRBM_GUI_ACTIVE")
-             + VALU_MIX} if issue_csv else {}
+    issue = {}
+    for path in (issue_csv.split(",") if issue_csv else []):  # one or more counter runs
+        for c in ("SQ_INSTS_VALU", "GRBM_GUI_ACTIVE") + VALU_MIX:
+            got = read_counter_csv(path, c)
+            if got:
+                issue[c] = got
     trace = read_trace_csv(trace_csv) if trace_csv else {}
 
     def pick(d, key):

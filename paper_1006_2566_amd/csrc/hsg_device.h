@@ -472,14 +472,27 @@ __device__ __forceinline__ Vec3<R> reflect(const Vec3<R>& s, const Vec3<R>& h) {
                  ok ? dev_fma(f, h.z, -s.z) : s.z};
 }
 
-// Sum of a double across the 64 lanes of a wavefront (butterfly; every lane ends
-// with the same value).  Within rows of 16 lanes the exchanges use DPP
-// (quad_perm and row mirrors); across rows they use ds_swizzle-free lane shuffles.
+// A double moved between lanes by one DPP control (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum of a double across the 64 lanes of a wavefront (every lane ends with the same
+// value).  Within rows of 16 lanes the exchanges are DPP moves: quad_perm [1,0,3,2]
+// (lane ^ 1) and [2,3,0,1] (lane ^ 2), after which the four lanes of a quad hold the
+// same bits (addition commutes), so the row half-mirror (lane i with 7 - i) and the
+// row mirror (i with 15 - i) bring in the neighbouring quad's and half-row's sums just
+// as lane ^ 4 and lane ^ 8 would; across rows, lane shuffles (^ 16, ^ 32).  The result
+// is the butterfly's, bit for bit.
 __device__ __forceinline__ double wave_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
-  v += __shfl_xor(v, 4);
-  v += __shfl_xor(v, 8);
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x141>(v);  // row_half_mirror
+  v += dpp_move<0x140>(v);  // row_mirror
   v += __shfl_xor(v, 16);
   v += __shfl_xor(v, 32);
   return v;
