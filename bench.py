@@ -33,16 +33,17 @@ _COMMON_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/c
 # the counters were taken from.
 DOMINANT = {
     "metropolis_pass": {
-        "kernel": "colour_pass_kernel<float, Metropolis>",
-        "trace_name": "colour_pass_kernel<float, (hsg::PassMode)0, false>",
+        # k a multiple of four: the instantiation whose hit groups are all complete
+        "kernel": "colour_pass_kernel<float, MetropolisFull>",
+        "trace_name": "colour_pass_kernel<float, (hsg::PassMode)3, false>",
         "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_sweep.hip",),
         "traffic_file": "profiles/traffic_metropolis_pass_L256_f32.txt",
         "title": "one Metropolis colour pass",
         "sites": 0.5,  # updated sites per launch, in units of N
     },
     "phase_mc": {
-        "kernel": "phase_kernel<float, 3, Metropolis>",
-        "trace_name": "phase_kernel<float, 3, (hsg::PassMode)0>",
+        "kernel": "phase_kernel<float, 3, MetropolisFull>",
+        "trace_name": "phase_kernel<float, 3, (hsg::PassMode)3>",
         "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_phase.hip",),
         "traffic_file": "profiles/traffic_phase_mc_L256_f32.txt",
         "title": "one over-relaxation phase with the next colour-0 Metropolis pass",
