@@ -14,8 +14,8 @@
 //   stage A   colour 0, over-relaxation, ring NS - 1, plane a
 //   stage B   colour 1, over-relaxation, ring NS - 2, plane a - 1 (reads colour 0 on
 //             a - 2 .. a)
-//   stage C   colour 0, Monte Carlo, the tile only, plane a - 2 (reads colour 1 on
-//             a - 3 .. a - 1)
+//   stage C   colour 0, Monte Carlo, the tile only, plane a - 3 (reads colour 1 on
+//             a - 4 .. a - 2, as stage B left them in earlier steps)
 //
 // The ring and the planes outside the tile's own belong to other workgroups, which
 // compute them too, from the same inputs and the same Philox draws, hence to the same
@@ -26,7 +26,7 @@
 // expensive Monte Carlo update is never recomputed, and the phase's spin traffic (the
 // planes in LDS) serves the Monte Carlo pass too, as do the couplings stage A loads for
 // the tile's sites: stage A takes those sites first, each thread the one it will update
-// in stage C two steps later, and keeps their six couplings.
+// in stage C three steps later, and keeps its six couplings and its spin in registers.
 //
 // The site arithmetic (field of eq. 2 in the fixed order of the single-pass kernel, then
 // the reflection of §4 or the k Metropolis hits / heat-bath draws) is the single pass's,
@@ -50,7 +50,7 @@ __device__ __forceinline__ int32_t wrap_to(int32_t v, int32_t n) {
 
 // The LDS window of a march with NS stages and THREADS threads.  Region column j holds
 // colour column xh0 - OX + j, region row ry holds row y0 - OY + ry.  Colour 0 keeps K0
-// planes, colour 1 K1 planes (stage C reads colour 1 on planes behind stage A's).
+// planes, colour 1 K1 planes.
 template <int NS, int K0_, int K1_, int THREADS_>
 struct Win {
   static constexpr int OX = NS - 1;
@@ -65,7 +65,25 @@ struct Win {
   static constexpr int LOAD_ROUNDS = (SLICE + THREADS - 1) / THREADS;
 };
 using WinPhase = Win<2, 3, 3, kPhaseThreads>;  // the phase
-using WinMc = Win<3, 3, 5, kPhaseThreads>;     // the phase and stage C
+using WinMc = Win<3, 3, 3, kPhaseThreads>;     // the phase and stage C
+
+// The carried pass's colour-1 planes after stage B, three of them in a ring: the sites
+// stage B updates (the tile widened by one row and one colour column on each side),
+// the only ones stage C reads.
+template <class W>
+struct Compact {
+  static constexpr int CX = kPTX + 2;
+  static constexpr int CY = kPTY + 2;
+  static constexpr int COLOUR = CX * CY;
+  static constexpr int SLICE = 3 * COLOUR;
+  static constexpr int X0 = W::OX - 1;  // region column of compact column 0
+  static constexpr int Y0 = W::OY - 1;  // region row of compact row 0
+};
+
+template <typename R, class W>
+__device__ __forceinline__ R* compact_slice(R* lds, int32_t q) {
+  return lds + (W::K0 + W::K1) * W::SLICE + ((q + 9) % 3) * Compact<W>::SLICE;
+}
 
 // The sites a stage with ring H updates on one plane: rows OY - H .. OY + kPTY + H - 1,
 // kPTX + H sites of the stage's colour in each.  On a row whose sites of that colour
@@ -245,27 +263,18 @@ __device__ __forceinline__ void fetch_bonds(StageBonds<R, W, S, T>& sb, const R*
           J, m, site_ref<W, St::C, St::H>(m, q, (int32_t)threadIdx.x + r * T));
 }
 
-// Update of the site of colour C at r on plane q: the field of eq. 2 from the window
-// (neighbour colour 1 - C) and the couplings jb, in the fixed order of the single-pass
-// kernel, then (optionally renormalising before or after) apply_update.  The result goes
-// back to the window when `keep`; with `own_out` the tile's sites are also written to
-// the output.
-template <typename R, class W, int C, PassMode MODE, int G>
-__device__ __forceinline__ double phase_site(R* lds, R* out, const PhaseCtx& m, int32_t q,
-                                             const SiteRef& r, const Bonds<R>& jb,
-                                             const HitCtx<R>& hc, bool renorm_before,
-                                             bool renorm_after, bool keep, bool own_out) {
-  const R* cur = slice<R, W>(lds, 1 - C, q);
-  const R* up = slice<R, W>(lds, 1 - C, q + 1);
-  const R* dn = slice<R, W>(lds, 1 - C, q - 1);
-  const int32_t j = r.j;
-  const int32_t row = r.ry * W::RX;
-  const int32_t i_px = row + (r.p ? j + 1 : j), i_mx = row + (r.p ? j : j - 1);
-  const int32_t i_py = row + W::RX + j, i_my = row - W::RX + j, i_z = row + j;
+// The local field of eq. 2 at a site from the spins of the other colour on three planes
+// (components `cs` values apart, neighbours at the given offsets) and its couplings, in
+// the fixed order of the single-pass kernel.
+template <typename R>
+__device__ __forceinline__ Vec3<R> plane_field(const R* cur, const R* up, const R* dn,
+                                               int32_t cs, int32_t i_px, int32_t i_mx,
+                                               int32_t i_py, int32_t i_my, int32_t i_z,
+                                               const Bonds<R>& jb) {
   R hcomp[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int32_t kb = k * W::COLOUR;
+    const int32_t kb = k * cs;
     R acc = jb.px * cur[kb + i_px];
     acc = dev_fma(jb.mx, cur[kb + i_mx], acc);
     acc = dev_fma(jb.py, cur[kb + i_py], acc);
@@ -274,7 +283,40 @@ __device__ __forceinline__ double phase_site(R* lds, R* out, const PhaseCtx& m, 
     acc = dev_fma(jb.mz, dn[kb + i_z], acc);
     hcomp[k] = acc;
   }
-  const Vec3<R> h{hcomp[0], hcomp[1], hcomp[2]};
+  return Vec3<R>{hcomp[0], hcomp[1], hcomp[2]};
+}
+
+__device__ __forceinline__ bool in_tile(int32_t ry, int32_t j, int32_t ox, int32_t oy) {
+  return ry >= oy && ry < oy + kPTY && j >= ox && j < ox + kPTX;
+}
+
+template <typename R>
+__device__ __forceinline__ void write_site(R* out, const PhaseCtx& m, int32_t c,
+                                           const SiteRef& r, const Vec3<R>& s) {
+  R* o = out + (uint32_t)(3 * c) * m.Nh + m.zstride * (uint32_t)r.z +
+         (uint32_t)m.Lh * (uint32_t)r.y + (uint32_t)r.xh;
+  o[0] = s.x;
+  o[m.Nh] = s.y;
+  o[2 * m.Nh] = s.z;
+}
+
+// Update of the site of colour C at r on plane q: the field of eq. 2 from the window
+// (neighbour colour 1 - C) and the couplings jb, then (optionally renormalising before
+// or after) apply_update.  The result goes back to the window when `keep` (with COMPACT,
+// to the compact plane q instead); with `own_out` the tile's sites are also written to
+// the output; with `spin_out` it is also returned there.
+template <typename R, class W, int C, PassMode MODE, int G, bool COMPACT = false>
+__device__ __forceinline__ double phase_site(R* lds, R* out, const PhaseCtx& m, int32_t q,
+                                             const SiteRef& r, const Bonds<R>& jb,
+                                             const HitCtx<R>& hc, bool renorm_before,
+                                             bool renorm_after, bool keep, bool own_out,
+                                             Vec3<R>* spin_out = nullptr) {
+  const int32_t j = r.j;
+  const int32_t row = r.ry * W::RX;
+  const Vec3<R> h = plane_field<R>(
+      slice<R, W>(lds, 1 - C, q), slice<R, W>(lds, 1 - C, q + 1), slice<R, W>(lds, 1 - C, q - 1),
+      W::COLOUR, row + (r.p ? j + 1 : j), row + (r.p ? j : j - 1), row + W::RX + j,
+      row - W::RX + j, row + j, jb);
   R* mine = slice<R, W>(lds, C, q);
   const int32_t io = row + j;
   Vec3<R> s{mine[io], mine[W::COLOUR + io], mine[2 * W::COLOUR + io]};
@@ -284,23 +326,51 @@ __device__ __forceinline__ double phase_site(R* lds, R* out, const PhaseCtx& m, 
   const double d = apply_update<R, MODE, G>(s, h, site, hc);
   if (renorm_after) s = unit_vector(s);
   if (keep) {
-    mine[io] = s.x;
-    mine[W::COLOUR + io] = s.y;
-    mine[2 * W::COLOUR + io] = s.z;
+    if constexpr (COMPACT) {
+      using CP = Compact<W>;
+      R* dst = compact_slice<R, W>(lds, q);
+      const int32_t ic = (r.ry - CP::Y0) * CP::CX + (j - CP::X0);
+      dst[ic] = s.x;
+      dst[CP::COLOUR + ic] = s.y;
+      dst[2 * CP::COLOUR + ic] = s.z;
+    } else {
+      mine[io] = s.x;
+      mine[W::COLOUR + io] = s.y;
+      mine[2 * W::COLOUR + io] = s.z;
+    }
   }
-  if (own_out && r.ry >= W::OY && r.ry < W::OY + kPTY && j >= W::OX && j < W::OX + kPTX) {
-    R* o = out + (uint32_t)(3 * C) * m.Nh + m.zstride * (uint32_t)r.z +
-           (uint32_t)m.Lh * (uint32_t)r.y + (uint32_t)r.xh;
-    o[0] = s.x;
-    o[m.Nh] = s.y;
-    o[2 * m.Nh] = s.z;
-  }
+  if (own_out && in_tile(r.ry, j, W::OX, W::OY)) write_site<R>(out, m, C, r, s);
+  if (spin_out) *spin_out = s;
+  return d;
+}
+
+// Stage C of the carried pass: the Monte Carlo update of colour-0 tile site r on plane q,
+// its spin s (after the over-relaxation phase) and couplings jb kept in registers since
+// stage A, the colour-1 neighbours from the compact planes q - 1 .. q + 1.  The result
+// goes to the output.
+template <typename R, class W, PassMode MODE, int G>
+__device__ __forceinline__ double carried_site(R* lds, R* out, const PhaseCtx& m, int32_t q,
+                                               const SiteRef& r, const Bonds<R>& jb, Vec3<R> s,
+                                               const HitCtx<R>& hc, bool renorm_before) {
+  using CP = Compact<W>;
+  const int32_t j = r.j - CP::X0;
+  const int32_t row = (r.ry - CP::Y0) * CP::CX;
+  const Vec3<R> h = plane_field<R>(
+      compact_slice<R, W>(lds, q), compact_slice<R, W>(lds, q + 1),
+      compact_slice<R, W>(lds, q - 1), CP::COLOUR, row + (r.p ? j + 1 : j),
+      row + (r.p ? j : j - 1), row + CP::CX + j, row - CP::CX + j, row + j, jb);
+  if (renorm_before) s = unit_vector(s);
+  const uint32_t site =
+      (uint32_t)(2 * r.xh + r.p) + (uint32_t)m.L * (uint32_t)(r.y + m.L * r.z);
+  const double d = apply_update<R, MODE, G>(s, h, site, hc);
+  write_site<R>(out, m, 0, r, s);
   return d;
 }
 
 // Every site of stage s on plane q, with the couplings fetched for it (sb), or with
 // PRE false loading each site's couplings just before its update (fewer registers).
-template <typename R, class W, int S, PassMode MODE, int G, int T, bool PRE>
+template <typename R, class W, int S, PassMode MODE, int G, int T, bool PRE,
+          bool COMPACT = false>
 __device__ __forceinline__ double stage(R* lds, const R* J, R* out, const PhaseCtx& m,
                                         int32_t q, const StageBonds<R, W, S, T>& sb,
                                         const HitCtx<R>& hc, bool renorm_before,
@@ -312,8 +382,8 @@ __device__ __forceinline__ double stage(R* lds, const R* J, R* out, const PhaseC
     if (St::has(r)) {
       const SiteRef ref = site_ref<W, St::C, St::H>(m, q, (int32_t)threadIdx.x + r * T);
       const Bonds<R> jb = PRE ? sb.b[r] : site_bonds<R, St::C>(J, m, ref);
-      d += phase_site<R, W, St::C, MODE, G>(lds, out, m, q, ref, jb, hc, renorm_before,
-                                            renorm_after, keep, own_out);
+      d += phase_site<R, W, St::C, MODE, G, COMPACT>(lds, out, m, q, ref, jb, hc, renorm_before,
+                                                     renorm_after, keep, own_out);
     }
   }
   return d;
@@ -353,106 +423,47 @@ __device__ __forceinline__ void prologue(R* lds, SliceRegs<R, W>& r0, SliceRegs<
   fetch<R, W>(r1, so, in, m, 1, m.z0 - NS + 3);
 }
 
-// NS = 2: the over-relaxation phase.  NS = 3: the phase, then the colour-0 pass of the
-// next sweep's Monte Carlo phase in mode MC.
-template <typename R, int NS, PassMode MC>
+// The over-relaxation phase alone (stages A and B): each step stage A on plane q, stage
+// B on plane q - 1, then the next planes into the window.  The couplings of a stage's
+// sites are loaded a step ahead (the loads stay in flight across the barriers).
+template <typename R>
 __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
-  using W = typename std::conditional<NS == 2, WinPhase, WinMc>::type;
+  using W = WinPhase;
   constexpr PassMode OR = PassMode::OverRelax;
   constexpr int T = kPhaseThreads;
-  constexpr int STEPS = kPZ + 2 * (NS - 1);
+  constexpr int STEPS = kPZ + 2;
   __shared__ R lds[(W::K0 + W::K1) * W::SLICE];
   const PhaseCtx m = phase_ctx(a.L, kPZ);
   const HitCtx<R> hc{a.beta, a.sweep, a.phase, a.k_hits, a.seed_lo, a.seed_hi};
-  const HitCtx<R> hm{a.beta, a.mc_sweep, 0u, a.k_hits, a.seed_lo, a.seed_hi};
-  const bool rn = NS == 3 && a.renorm != 0;
   SliceOffsets<W> so;
   slice_offsets<W>(so, m);
   SliceRegs<R, W> r0, r1;
-  prologue<R, W, NS>(lds, r0, r1, so, a.in, m);
-  // The phase alone loads the couplings of its stages' sites a step ahead (the loads
-  // stay in flight across the barriers).  With stage C, stages A and B load each site's
-  // just before its update (holding them across stage C would cost the registers of the
-  // second workgroup per compute unit, which measures slower), and stage C takes its
-  // sites' from stage A, which loaded them two steps earlier.
-  constexpr bool PF = NS == 2;
+  prologue<R, W, 2>(lds, r0, r1, so, a.in, m);
   StageBonds<R, W, 0, T> bA;
   StageBonds<R, W, 1, T> bB;
-  if (PF) fetch_bonds<R, W, 0, T>(bA, a.J, m, m.z0 - 1);
-
-  double dE = 0.0;
-  // NS = 3: the six couplings of this thread's tile site as stage A loaded them on the
-  // last three planes (own0: this step's plane, own2: stage C's)
-  Bonds<R> own0{}, own1{}, own2{};
+  fetch_bonds<R, W, 0, T>(bA, a.J, m, m.z0 - 1);
   for (int32_t t = 0; t < STEPS; ++t) {
-    const int32_t q = m.z0 - (NS - 1) + t;  // stage A's plane; stage B on q - 1, C on q - 2
+    const int32_t q = m.z0 - 1 + t;  // stage A's plane; stage B on q - 1
     __syncthreads();
-    // NS = 3: waves take a priority by stage -- 3 in stage A and the plane fetches, 2 in
-    // stage B, 0 in the Metropolis stage.  While the two workgroups on a compute unit are
-    // in different stages, one of them then issues first instead of both sharing the
-    // issue slots: 2-4% per launch (about the same with the order reversed, none with one
-    // priority throughout); B below A adds 1-2% at k = 1.
-    if constexpr (NS == 3) __builtin_amdgcn_s_setprio(3);
-    // the phase alone: colour 0 of plane q is final after stage A, its tile goes out
-    // from there
-    const bool own_a = NS == 2 && q >= m.z0 && q < m.z0 + kPZ;
-    if constexpr (NS == 3) {
-#pragma unroll
-      for (int r = 0; r < (StageShape<W, 2>::COUNT + T - 1) / T; ++r) {
-        const int32_t i = (int32_t)threadIdx.x + r * T;
-        if (i < StageShape<W, 2>::COUNT) {
-          const SiteRef ref = site_ref_a3<W>(m, q, i);
-          const Bonds<R> jb = site_bonds<R, 0>(a.J, m, ref);
-          if (r == 0) own0 = jb;
-          phase_site<R, W, 0, OR, 1>(lds, a.out, m, q, ref, jb, hc, false, false, true, false);
-        }
-      }
-    } else {
-      stage<R, W, 0, OR, 1, T, PF>(lds, a.J, a.out, m, q, bA, hc, false, false, true, own_a);
-    }
-    if (PF && t + 1 < STEPS) fetch_bonds<R, W, 0, T>(bA, a.J, m, q + 1);
-    if (PF && t == 1) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
+    // colour 0 of plane q is final after stage A: its tile goes out from there
+    const bool own_a = q >= m.z0 && q < m.z0 + kPZ;
+    stage<R, W, 0, OR, 1, T, true>(lds, a.J, a.out, m, q, bA, hc, false, false, true, own_a);
+    if (t + 1 < STEPS) fetch_bonds<R, W, 0, T>(bA, a.J, m, q + 1);
+    if (t == 1) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
     __syncthreads();
-    if constexpr (NS == 2) {
-      if (t >= 2) {
-        // colour 1 of plane q - 1 is final after stage B and read by no later stage: its
-        // tile goes out from there, nothing back to the window
-        const bool own = q - 1 >= m.z0 && q - 1 < m.z0 + kPZ;
-        stage<R, W, 1, OR, 1, T, true>(lds, a.J, a.out, m, q - 1, bB, hc, false, false, false,
-                                       own);
-        if (t + 1 < STEPS) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
-      }
-      __syncthreads();
-      // colour 0 of plane q + 1 replaces plane q - 2 (last read by stage B)
-      if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
-    } else {
-      __builtin_amdgcn_s_setprio(2);
-      if (t >= 2) {
-        // colour 1 of plane q - 1 is final after stage B: its tile goes out from there
-        const bool own = q - 1 >= m.z0 && q - 1 < m.z0 + kPZ;
-        stage<R, W, 1, OR, 1, T, false>(lds, a.J, a.out, m, q - 1, bB, hc, false, rn, true,
-                                        own);
-      }
-      __syncthreads();
-      __builtin_amdgcn_s_setprio(0);
-      // colour 0 of plane q - 2 (one of the tile's own planes) after stage C is final
-      if (t >= 4) {
-        // the tile site of this thread: its own bonds from stage A two steps ago
-        const SiteRef ref = site_ref<W, 0, 0>(m, q - 2, (int32_t)threadIdx.x);
-        dE += phase_site<R, W, 0, MC, kHitGroup>(lds, a.out, m, q - 2, ref, own2, hm, rn, false,
-                                                 false, true);
-      }
-      __builtin_amdgcn_s_setprio(3);
-      __syncthreads();
-      // colour 0 of plane q + 1 replaces plane q - 2, read by stage C above
-      if (t < STEPS - 1) put<R, W>(lds, r0, 0, q + 1);
+    if (t >= 2) {
+      // colour 1 of plane q - 1 is final after stage B and read by no later stage: its
+      // tile goes out from there, nothing back to the window
+      const bool own = q - 1 >= m.z0 && q - 1 < m.z0 + kPZ;
+      stage<R, W, 1, OR, 1, T, true>(lds, a.J, a.out, m, q - 1, bB, hc, false, false, false,
+                                     own);
+      if (t + 1 < STEPS) fetch_bonds<R, W, 1, T>(bB, a.J, m, q);
     }
-    if constexpr (NS == 3) {
-      own2 = own1;
-      own1 = own0;
-    }
-    // colour 1 of plane q + 2 replaces plane q + 2 - K1 (last read this step)
+    __syncthreads();
     if (t < STEPS - 1) {
+      // colour 0 of plane q + 1 replaces plane q - 2 (last read by stage B), colour 1 of
+      // plane q + 2 replaces plane q - 1 (last read this step)
+      put<R, W>(lds, r0, 0, q + 1);
       put<R, W>(lds, r1, 1, q + 2);
       if (t < STEPS - 2) {
         fetch<R, W>(r0, so, a.in, m, 0, q + 2);
@@ -460,17 +471,123 @@ __global__ __launch_bounds__(kPhaseThreads) void phase_kernel(PhaseArgs<R> a) {
       }
     }
   }
-  if constexpr (NS == 3) {
-    __shared__ double s_red[16];
-    const double total = block_sum(dE, s_red);
-    if (threadIdx.x == 0) a.partials[blockIdx.x] += total;
-  }
 }
 
-template <typename R, int NS, PassMode MC>
-hipError_t launch_ns(const PhaseArgs<R>& a, hipStream_t st) {
+// The phase, then the colour-0 pass of the next sweep's Monte Carlo phase in mode MC
+// (stage C), each step in three intervals between barriers:
+//
+//   1. stage C on plane q - 3, then stage A on plane q
+//   2. stage B on plane q - 1, its results to the compact plane q - 1
+//   3. the next planes into the window
+//
+// Stage C reads colour 1 only from the compact planes q - 4 .. q - 2, which stage B
+// finished in earlier steps, so it shares an interval with stage A, and its own spins
+// and couplings come from registers: this thread's tile site as stage A left it three
+// steps earlier.  So the window keeps three planes of each colour.
+template <typename R, PassMode MC>
+__global__ __launch_bounds__(kPhaseThreads)
+__attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 4 : 2))) void phase_mc_kernel(PhaseArgs<R> a) {
+  using W = WinMc;
+  using CP = Compact<W>;
+  using StA = StageShape<W, 2>;
+  constexpr PassMode OR = PassMode::OverRelax;
+  constexpr int T = kPhaseThreads;
+  constexpr int RA = (StA::COUNT + T - 1) / T;  // stage A rounds
+  constexpr int LAST_A = kPZ + 3;                // stage A on planes z0 - 2 .. z0 + kPZ + 1
+  constexpr int FIRST_C = 5;                     // stage C on planes z0 .. z0 + kPZ - 1
+  constexpr int STEPS = kPZ + FIRST_C;
+  // binary32 keeps stage C's couplings in registers from stage A; binary64 (one
+  // workgroup per compute unit, twice the registers per value) loads them again
+  constexpr bool KEEP_BONDS = sizeof(R) == 4;
+  static_assert(T == kPTX * kPTY, "one stage-C site per thread");
+  __shared__ R lds[(W::K0 + W::K1) * W::SLICE + 3 * CP::SLICE];
+  const PhaseCtx m = phase_ctx(a.L, kPZ);
+  const HitCtx<R> hc{a.beta, a.sweep, a.phase, a.k_hits, a.seed_lo, a.seed_hi};
+  const HitCtx<R> hm{a.beta, a.mc_sweep, 0u, a.k_hits, a.seed_lo, a.seed_hi};
+  const bool rn = a.renorm != 0;
+  SliceOffsets<W> so;
+  slice_offsets<W>(so, m);
+  SliceRegs<R, W> r0, r1;
+  prologue<R, W, 3>(lds, r0, r1, so, a.in, m);
+  StageBonds<R, W, 1, T> unused;
+  // this thread's tile site as stage A left it one, two and three steps ago
+  Bonds<R> b1{}, b2{}, b3{};
+  Vec3<R> s1{}, s2{}, s3{};
+  double dE = 0.0;
+  for (int32_t t = 0; t < STEPS; ++t) {
+    const int32_t q = m.z0 - 2 + t;  // stage A's plane; stage B on q - 1, C on q - 3
+    __syncthreads();
+    // Interval 1: stage C, then stage A (stage C consumes the oldest registers before
+    // stage A fills new ones).  Waves take a priority by stage (0 in stage C, 3 in stage
+    // A and the plane loads, 2 in stage B), so that one of the two workgroups on a compute
+    // unit issues first while they are in different stages.
+    if (t >= FIRST_C) {
+      __builtin_amdgcn_s_setprio(0);
+      const SiteRef ref = site_ref<W, 0, 0>(m, q - 3, (int32_t)threadIdx.x);
+      const Bonds<R> jb = KEEP_BONDS ? b3 : site_bonds<R, 0>(a.J, m, ref);
+      dE += carried_site<R, W, MC, kHitGroup>(lds, a.out, m, q - 3, ref, jb, s3, hm, rn);
+    }
+    Bonds<R> b0 = b1;
+    Vec3<R> s0 = s1;
+    if (t <= LAST_A) {
+      __builtin_amdgcn_s_setprio(3);
+#pragma unroll
+      for (int r = 0; r < RA; ++r) {
+        const int32_t i = (int32_t)threadIdx.x + r * T;
+        if (i < StA::COUNT) {
+          const SiteRef ref = site_ref_a3<W>(m, q, i);
+          const Bonds<R> jb = site_bonds<R, 0>(a.J, m, ref);
+          if (KEEP_BONDS && r == 0) b0 = jb;
+          phase_site<R, W, 0, OR, 1>(lds, a.out, m, q, ref, jb, hc, false, false, true, false,
+                                     r == 0 ? &s0 : nullptr);
+        }
+      }
+    }
+    b3 = b2;
+    b2 = b1;
+    b1 = b0;
+    s3 = s2;
+    s2 = s1;
+    s1 = s0;
+    __syncthreads();
+    // Interval 2: stage B.  Colour 1 of plane q - 1 is final: its tile goes out from
+    // there, the sites stage C reads to the compact plane.
+    if (t >= 2 && t <= LAST_A) {
+      __builtin_amdgcn_s_setprio(2);
+      const bool own = q - 1 >= m.z0 && q - 1 < m.z0 + kPZ;
+      stage<R, W, 1, OR, 1, T, false, true>(lds, a.J, a.out, m, q - 1, unused, hc, false, rn,
+                                            true, own);
+    }
+    __syncthreads();
+    // Interval 3: colour 0 of plane q + 1 replaces plane q - 2 and colour 1 of plane q + 2
+    // replaces plane q - 1, both last read by stage B above; the planes of the next step's
+    // end are loaded (in flight through the next step).
+    __builtin_amdgcn_s_setprio(3);
+    if (t < LAST_A) {
+      put<R, W>(lds, r0, 0, q + 1);
+      put<R, W>(lds, r1, 1, q + 2);
+      if (t + 1 < LAST_A) {
+        fetch<R, W>(r0, so, a.in, m, 0, q + 2);
+        fetch<R, W>(r1, so, a.in, m, 1, q + 3);
+      }
+    }
+  }
+  __shared__ double s_red[16];
+  const double total = block_sum(dE, s_red);
+  if (threadIdx.x == 0) a.partials[blockIdx.x] += total;
+}
+
+template <typename R>
+hipError_t launch_alone(const PhaseArgs<R>& a, hipStream_t st) {
   const dim3 grid((unsigned)phase_blocks(a.L)), block(kPhaseThreads);
-  hipLaunchKernelGGL((phase_kernel<R, NS, MC>), grid, block, 0, st, a);
+  hipLaunchKernelGGL((phase_kernel<R>), grid, block, 0, st, a);
+  return hipGetLastError();
+}
+
+template <typename R, PassMode MC>
+hipError_t launch_mc(const PhaseArgs<R>& a, hipStream_t st) {
+  const dim3 grid((unsigned)phase_blocks(a.L)), block(kPhaseThreads);
+  hipLaunchKernelGGL((phase_mc_kernel<R, MC>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 
@@ -486,14 +603,14 @@ int32_t phase_blocks(int32_t L) { return (L / 2 / kPTX) * (L / kPTY) * (L / kPZ)
 template <typename R>
 hipError_t launch_phase(const PhaseArgs<R>& a, hipStream_t st) {
   if (!phase_supported(a.L)) return hipErrorInvalidValue;
-  if (!a.then_mc) return launch_ns<R, 2, PassMode::OverRelax>(a, st);
+  if (!a.then_mc) return launch_alone<R>(a, st);
   if (!a.partials) return hipErrorInvalidValue;
   const PassMode mc = (PassMode)a.mc_mode == PassMode::HeatBath ? PassMode::HeatBath
                        : metropolis_mode(a.k_hits);
   if ((PassMode)a.mc_mode == PassMode::OverRelax) return hipErrorInvalidValue;
-  if (mc == PassMode::MetropolisFull) return launch_ns<R, 3, PassMode::MetropolisFull>(a, st);
-  if (mc == PassMode::Metropolis) return launch_ns<R, 3, PassMode::Metropolis>(a, st);
-  return launch_ns<R, 3, PassMode::HeatBath>(a, st);
+  if (mc == PassMode::MetropolisFull) return launch_mc<R, PassMode::MetropolisFull>(a, st);
+  if (mc == PassMode::Metropolis) return launch_mc<R, PassMode::Metropolis>(a, st);
+  return launch_mc<R, PassMode::HeatBath>(a, st);
 }
 
 template hipError_t launch_phase<float>(const PhaseArgs<float>&, hipStream_t);
