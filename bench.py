@@ -42,8 +42,8 @@ DOMINANT = {
         "sites": 0.5,  # updated sites per launch, in units of N
     },
     "phase_mc": {
-        "kernel": "phase_kernel<float, 3, MetropolisFull>",
-        "trace_name": "phase_kernel<float, 3, (hsg::PassMode)3>",
+        "kernel": "phase_mc_kernel<float, MetropolisFull>",
+        "trace_name": "phase_mc_kernel<float, (hsg::PassMode)3>",
         "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_phase.hip",),
         "traffic_file": "profiles/traffic_phase_mc_L256_f32.txt",
         "title": "one over-relaxation phase with the next colour-0 Metropolis pass",
@@ -52,8 +52,8 @@ DOMINANT = {
         "sites": 1.5,
     },
     "phase": {
-        "kernel": "phase_kernel<float, 2, OverRelax>",
-        "trace_name": "phase_kernel<float, 2, (hsg::PassMode)1>",
+        "kernel": "phase_kernel<float>",
+        "trace_name": "phase_kernel<float>(",
         "sources": _COMMON_SOURCES + ("paper_1006_2566_amd/csrc/kernels_phase.hip",),
         "traffic_file": "profiles/traffic_phase_L256_f32.txt",
         "title": "one over-relaxation phase",
@@ -144,15 +144,28 @@ def read_counter_csv(path, counter=None):
     return out
 
 
-def read_trace_csv(path):
-    """{kernel name: [duration in us per dispatch]} from rocprofv3's kernel_trace.csv."""
+def read_trace_csv(path, isolated_gap_us=2.0):
+    """{kernel name: [duration in us per dispatch]} from rocprofv3's kernel_trace.csv, and
+    the same for the dispatches that start at least isolated_gap_us after the previous
+    dispatch of the queue ended.  The latter are the launches hsg_sweep_timed brackets
+    with events (their markers leave such a gap); under the profiler, launches that follow
+    each other with no gap run longer than the same launches without it, which is not so
+    without the profiler (the plain sweep time equals the sum of the event-timed launches
+    there)."""
     import csv
-    out = {}
+    out, isolated = {}, {}
     with open(path, newline="") as f:
-        for row in csv.DictReader(f):
-            d = (int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-3
-            out.setdefault(row["Kernel_Name"], []).append(d)
-    return out
+        rows = sorted(csv.DictReader(f), key=lambda r: int(r["Start_Timestamp"]))
+    prev_end = {}
+    for row in rows:
+        q = row.get("Queue_Id", "")
+        start, end = int(row["Start_Timestamp"]), int(row["End_Timestamp"])
+        d = (end - start) * 1e-3
+        out.setdefault(row["Kernel_Name"], []).append(d)
+        if q in prev_end and (start - prev_end[q]) * 1e-3 >= isolated_gap_us:
+            isolated.setdefault(row["Kernel_Name"], []).append(d)
+        prev_end[q] = end
+    return out, isolated
 
 
 # vector instruction classes counted beside SQ_INSTS_VALU for the issue mix
@@ -173,7 +186,7 @@ def reduce_counters(fetch_csv, write_csv, issue_csv=None, trace_csv=None):
             got = read_counter_csv(path, c)
             if got:
                 issue[c] = got
-    trace = read_trace_csv(trace_csv) if trace_csv else {}
+    trace, trace_iso = read_trace_csv(trace_csv) if trace_csv else ({}, {})
 
     def pick(d, key):
         names = [n for n in d if key(n)]
@@ -231,6 +244,10 @@ def reduce_counters(fetch_csv, write_csv, issue_csv=None, trace_csv=None):
         t = pick(trace, match)
         if t:
             lines.append(f"trace_dispatches={len(t)} trace_mean_us={mean(t):.2f}")
+            ti = pick(trace_iso, match)
+            if ti:
+                lines.append(f"trace_isolated_dispatches={len(ti)} "
+                             f"trace_isolated_mean_us={mean(ti):.2f}")
         lines.append(f"source_hash={source_hash(name)}")
         with open(os.path.join(ROOT, d["traffic_file"]), "w") as f:
             f.write("\n".join(lines) + "\n")
@@ -583,6 +600,9 @@ def kernel_roofline(kind: int, stats: dict, N: int, counted: bool, brief: bool =
             "mix": kv.get("valu_mix", "")}
     if kv and "trace_mean_us" in kv:
         out["kernel_ms_rocprofv3"] = float(kv["trace_mean_us"]) * 1e-3
+    if kv and "trace_isolated_mean_us" in kv:
+        # the dispatches the event-timed call made (see read_trace_csv)
+        out["kernel_ms_rocprofv3_event_call"] = float(kv["trace_isolated_mean_us"]) * 1e-3
     return out
 
 
