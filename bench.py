@@ -25,6 +25,10 @@ sys.path.insert(0, ROOT)
 METRIC = "spin updates/ns at L=256 FP32 (k=1,4,8) + %HBM roofline; batched p50/p99 latency"
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 BYTES_PER_SITE_PHASE = 36.0  # binary32: read spin (12) + 3 bonds (12), write spin (12)
+# the other byte models per site-phase: a phase as two colour passes, each reading all six
+# coupling planes, its own spins and the other colour's (60 B); every neighbour and bond
+# read from memory at every site (120 B)
+BYTE_MODELS = {"algorithmic_36B": 36.0, "two_pass_60B": 60.0, "naive_120B": 120.0}
 _COMMON_SOURCES = ("paper_1006_2566_amd/csrc/hsg_site.h", "paper_1006_2566_amd/csrc/hsg_device.h",
                    "paper_1006_2566_amd/csrc/hsg_internal.h")
 # The kernels that can dominate the headline sweep: the binary32 Metropolis colour pass,
@@ -729,6 +733,23 @@ def main():
     copy = copy_bandwidth(torch)
     roofline["copy_GBs"] = copy
     roofline["frac_of_copy"] = roofline["achieved"] / copy
+    # the headline sweep against each byte model: fraction of the HBM peak and of the
+    # measured copy bandwidth
+    for kk, rec_k in per_k.items():
+        gb_per_s = {m: N * (1 + args.n_or) * b / (rec_k["ms_per_step"] * 1e-3) / 1e9
+                    for m, b in BYTE_MODELS.items()}
+        rec_k["byte_models"] = {m: {"GBs": v, "frac_of_peak": v / HBM_PEAK_GBS,
+                                    "frac_of_copy": v / copy} for m, v in gb_per_s.items()}
+    # counter-measured bytes of one steady-state sweep of the default traversal (one
+    # Metropolis colour pass + one phase launch carrying the next colour-0 pass)
+    kv_mc, kv_ph = counter_summary("metropolis_pass"), counter_summary("phase_mc")
+    if L == 256 and args.k == 4 and args.n_or == 1 and kv_mc and kv_ph and \
+            dom_kind == 4:
+        measured = sum(float(kv[f]) for kv in (kv_mc, kv_ph)
+                       for f in ("fetch_bytes_per_launch", "write_bytes_per_launch"))
+        roofline["sweep_bytes_measured"] = measured
+        roofline["sweep_bytes_measured_vs_36B"] = measured / (N * (1 + args.n_or) *
+                                                              BYTES_PER_SITE_PHASE)
     # the other kinds of launch of the headline sweep against the same roofline
     roofline["others"] = {hsg.LAUNCH_NAMES[kd]: kernel_roofline(kd, launches[kd], N, counted=False,
                                                                 brief=True)
