@@ -56,6 +56,10 @@ def lib():
             getattr(L, f"hsgo_init_{suf}").argtypes = [_I32, _U64, _P, _P]
             getattr(L, f"hsgo_local_field_{suf}").argtypes = [_I32, _P, _P, _I32, _I32, _I32, _P]
             getattr(L, f"hsgo_overrelax_site_{suf}").argtypes = [_P, _P]
+            getattr(L, f"hsgo_field_{suf}").argtypes = [_P, _P, _P]
+            fn = getattr(L, f"hsgo_site_update_{suf}")
+            fn.argtypes = [_I32, _P, _P, _U64, _U64, _U32, _U32, _I32, _D, _D, _P, _P]
+            fn.restype = _I64
             getattr(L, f"hsgo_elem_many_{suf}").argtypes = [_I32, _I64, _P, _P]
             getattr(L, f"hsgo_heat_bath_draw_{suf}").argtypes = [_P, real, real, real, _P]
             getattr(L, f"hsgo_elem_consts_{suf}").argtypes = [_P, _P, _P]
@@ -178,6 +182,28 @@ def local_field(L: int, spins: np.ndarray, J: np.ndarray, x: int, y: int, z: int
     getattr(lib(), f"hsgo_local_field_{_suf(spins.dtype)}")(
         L, _ptr(np.ascontiguousarray(spins)), _ptr(np.ascontiguousarray(J)), x, y, z, _ptr(h))
     return h
+
+
+def field(Jn, nbs, dtype=np.float64) -> np.ndarray:
+    """Local field from a site's six couplings Jn (+x, -x, +y, -y, +z, -z) and its six
+    neighbours' spins nbs (shape (6, 3), same order), in the order of local_field."""
+    jn = np.ascontiguousarray(np.asarray(Jn, dtype=dtype))
+    nb = np.ascontiguousarray(np.asarray(nbs, dtype=dtype).reshape(18))
+    h = np.zeros(3, dtype=dtype)
+    getattr(lib(), f"hsgo_field_{_suf(dtype)}")(_ptr(jn), _ptr(nb), _ptr(h))
+    return h
+
+
+def site_update(mode: int, h, s, *, seed: int, sweep: int, site: int, phase: int, k: int,
+                T: float, margin_eps: float = 1e-6, dtype=np.float64):
+    """One site's update as the sweep makes it (mode 0 Metropolis, 1 over-relaxation,
+    2 heat bath): returns (new spin, number of flagged decisions)."""
+    hh = np.ascontiguousarray(np.asarray(h, dtype=dtype))
+    out = np.array(s, dtype=dtype, copy=True)
+    fl = getattr(lib(), f"hsgo_site_update_{_suf(dtype)}")(
+        int(mode), _ptr(hh), _ptr(out), int(seed), int(sweep), int(site), int(phase), int(k),
+        float(T), float(margin_eps), None, None)
+    return out, int(fl)
 
 
 def overrelax_site(h, s) -> np.ndarray:

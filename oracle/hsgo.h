@@ -74,8 +74,13 @@ int hsgo_pt_swap(int32_t n_temps, const double *beta_of_slot, const double *E_of
   void hsgo_sincos_2pi_##SUF(R u, R *sin_out, R *cos_out);                                    \
   void hsgo_trial_spin_##SUF(R u0, R u1, R s[3]);                                             \
   void hsgo_init_##SUF(int32_t L, uint64_t seed, R *spins, R *J);                             \
+  void hsgo_field_##SUF(const R Jn[6], const R nbs[18], R h[3]);                             \
   void hsgo_local_field_##SUF(int32_t L, const R *spins, const R *J, int32_t x, int32_t y,    \
                               int32_t z, R h[3]);                                             \
+  int64_t hsgo_site_update_##SUF(int32_t mode, const R h[3], R s[3], uint64_t seed,           \
+                                 uint64_t sweep, uint32_t site, uint32_t phase,              \
+                                 int32_t k_hits, double T, double margin_eps, double *dE,    \
+                                 int64_t *accepted);                                          \
   void hsgo_overrelax_site_##SUF(const R h[3], R s[3]);                                       \
   R hsgo_exp_##SUF(R x);                                                                      \
   R hsgo_expm1_##SUF(R x);                                                                    \
