@@ -311,6 +311,29 @@ def binary64_leg(hsg, args, torch, flags):
             "spin_updates_per_ns": L ** 3 * (args.k + args.n_or) / (ms * 1e6)}
 
 
+# The paper's Table 2 (over-relaxation only, L = 128, binary32, 100 iterations): its GPU
+# figures, ns per spin update, with the GPUs of its hardware table (context, other hardware)
+PAPER_TABLE2_NS = {"GTX 480, TEXT (its best)": 0.63, "GTX 480, GM": 0.66,
+                   "GTX 480, SM4P": 0.86, "Tesla C1060, TEXT": 1.8, "Tesla C1060, GM": 1.9}
+
+
+def paper_workload_leg(hsg, torch):
+    """The paper's benchmark workload on this GPU: over-relaxation sweeps only (both
+    colours, no renormalisation) of an L = 128 binary32 lattice with Gaussian couplings,
+    100 iterations after 5 warm-up ones, the library's default traversal for that L."""
+    L, n = 128, 100
+    lat = hsg.Lattice(L, torch.float32, seed=1)
+    flags = hsg.default_flags(L, torch.float32)
+    ms = time_sweeps(lat, torch, T=1.0, k=0, n_or=1, R=0, steps=n, warmup=5, flags=flags)
+    ns_per_update = ms * 1e6 / L ** 3
+    del lat
+    return {"workload": "over-relaxation only, L=128, binary32, 100 iterations (the paper's "
+                        "Table 2 benchmark)", "flags": flags, "ms_per_sweep": ms,
+            "ns_per_update": ns_per_update, "updates_per_ns": 1.0 / ns_per_update,
+            "paper_ns_per_update": PAPER_TABLE2_NS,
+            "note": "the paper's figures are other hardware: context, not the target"}
+
+
 def heat_bath_leg(hsg, lat, torch, args, flags):
     """The headline sweep with a heat-bath draw in place of the Metropolis hits (same
     traversal).  A heat-bath draw does not depend on the spin it replaces, so a site
@@ -783,6 +806,10 @@ def main():
     if not args.no_heat_bath:
         rec["heat_bath"] = heat_bath_leg(hsg, lat, torch, args, flags)
         note("heat-bath leg done")
+    if args.large_L:  # with the other extra lattice sizes
+        rec["paper_workload"] = paper_workload_leg(hsg, torch)
+        note(f"paper workload: {rec['paper_workload']['ns_per_update'] * 1e3:.2f} ps per "
+             f"update")
     if not args.no_observables:
         rec["observables"] = observables_leg(hsg, lat, torch, args.steps)
         note("observables leg done")
