@@ -435,6 +435,11 @@ def batched_leg(args, torch):
     ms_plain = t0.elapsed_time(t1)
     upd_plain = sum(l.N for l in lats) * 4 * 2 / (ms_plain * 1e6)
     acc = pt.accepted.sum().item() / max(1, int(pt.round.item())) / pt.n_ladders
+    # each chain's tracked energy (binary64 sums of its binary32 energy changes) against a
+    # binary64 recomputation of its final binary32 state, after the timed cycles
+    E_tr = b.energies().double().cpu().numpy()
+    E_re = b.energies(recompute=True).double().cpu().numpy()
+    rel = np.abs(E_tr - E_re) / np.maximum(np.abs(E_re), 1e-300)
     return {"workload": "256 samples x 2 replicas x 24 temperatures (12288 chains, "
                         f"{sites:.3g} spins), L in {{16,24,32,48}}, binary32, k=4, exchange "
                         "every 10 sweeps, overlap every 100, one graph per 100 sweeps",
@@ -443,6 +448,9 @@ def batched_leg(args, torch):
             "plain_per_lattice_updates_per_ns": upd_plain,
             "speedup_vs_plain": upd / upd_plain,
             "exchange_acceptance_per_pair_round": acc,
+            "energy_tracked_vs_binary64_recompute": {
+                "chains": int(rel.size), "max_rel": float(rel.max()),
+                "median_rel": float(np.median(rel))},
             "threads": b.threads}
 
 
@@ -474,6 +482,7 @@ def served_leg(args, torch):
         wall = time.perf_counter() - t0
         work = float(sum(r.L ** 3 * r.sweeps * r.k for r in tr))
         st = S.latency_stats(res)
+        serve.results = res
         return {"requests": len(tr), "rate_per_s": len(tr) / tr[-1].arrival,
                 "p50_latency_s": st["p50_s"], "p99_latency_s": st["p99_s"],
                 "mean_latency_s": st["mean_s"], "wall_s": wall,
@@ -483,6 +492,7 @@ def served_leg(args, torch):
                               for k, v in srv.stats.items()}}
 
     main = serve(trace)
+    served_E = {r.rid: r.E for r in serve.results}
     capacity = main["spin_updates_per_ns"]
     main["rho"] = main["offered_updates_per_ns"] / capacity
     sweep = {}
@@ -496,19 +506,31 @@ def served_leg(args, torch):
                  f"p99 {r['p99_latency_s']:.3f} s, rho {r['rho']:.2f}")
     sample = trace[::10]
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    elapsed = 0.0
+    err_re, err_served = [], []
     for r in sample:
+        t1 = time.perf_counter()
         lat = hsg.Lattice(r.L, torch.float32, seed=r.seed)
         lat.sweep(T=r.T, k=r.k, n_or=0, n_sweeps=r.sweeps)
-        lat.energy().item()
+        E_tr = lat.energy().item()
+        elapsed += time.perf_counter() - t1
+        # not timed: the result's energy against a binary64 recomputation of the final
+        # binary32 state, and the served run's result against this one
+        E_re = lat.energy(recompute=True).item()
+        err_re.append(abs(E_tr - E_re) / max(abs(E_re), 1e-300))
+        err_served.append(abs(served_E[r.rid] - E_tr) / max(abs(E_re), 1e-300))
         del lat
-    torch.cuda.synchronize()
-    plain = sum(r.L ** 3 * r.sweeps * r.k for r in sample) / ((time.perf_counter() - t1) * 1e9)
+    plain = sum(r.L ** 3 * r.sweeps * r.k for r in sample) / (elapsed * 1e9)
     return {"workload": f"{len(trace)} requests, Poisson 200/s, L in {{8,16,32,64,96}}, "
                         "T in [0.1,1], sweeps log-uniform [100,1e4], k in {1,4}, binary32",
             **{k: v for k, v in main.items() if k != "scheduler"},
             "plain_per_lattice_updates_per_ns": plain,
             "plain_sample": f"every 10th request of the trace ({len(sample)} requests)",
+            "energy_error": {
+                "results": len(sample),
+                "tracked_vs_binary64_recompute_max_rel": max(err_re),
+                "tracked_vs_binary64_recompute_median_rel": sorted(err_re)[len(err_re) // 2],
+                "served_vs_alone_max_rel": max(err_served)},
             "speedup_vs_plain": capacity / plain, "budget_mb": args.serve_budget_mb,
             "step_sweeps": args.serve_step, "tile_sites": tile,
             "load_sweep": sweep, "scheduler": main["scheduler"]}
