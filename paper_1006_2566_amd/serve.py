@@ -22,6 +22,7 @@ import bisect
 import ctypes
 import dataclasses
 import math
+import threading
 import time
 from collections import deque
 
@@ -59,10 +60,33 @@ class Result:
     finished: float
     admitted_step: int = -1  # scheduler iteration of admission
     finished_step: int = -1  # scheduler iteration that saw the lattice finished
+    # "ok"; "cancelled" (E and m of the sweeps done, NaN if none were admitted);
+    # "rejected: <reason>" (never admitted, E and m NaN)
+    status: str = "ok"
+    sweeps_done: int = -1  # sweeps the lattice made (-1: never admitted)
 
     @property
     def latency(self) -> float:
         return self.finished - self.arrival
+
+
+def request_problem(req: Request, capacity_elements: int) -> str | None:
+    """Why a request cannot be served (None if it can): L even in [2, BATCH_L_MAX], at
+    least one Metropolis hit, T > 0 (T = inf means beta = 0), sweeps >= 0, a 64-bit
+    seed, and a lattice whose 3 L^3 elements fit the spin (and coupling) arena."""
+    if not (isinstance(req.L, int) and 2 <= req.L <= BATCH_L_MAX and req.L % 2 == 0):
+        return f"L={req.L} must be even in [2, {BATCH_L_MAX}]"
+    if not (1 <= req.k <= 0xFFFF):
+        return f"k={req.k} must be in [1, 65535]"
+    if not (req.T > 0):
+        return f"T={req.T} must be > 0"
+    if req.sweeps < 0 or req.sweeps > 0x7FFFFFFF:
+        return f"sweeps={req.sweeps} out of range"
+    if not (0 <= req.seed < 2 ** 64):
+        return f"seed={req.seed} must fit 64 bits"
+    if -(-3 * req.L ** 3 // 64) * 64 > capacity_elements:  # the arena's 64-element blocks
+        return f"footprint of L={req.L} exceeds the device-memory budget"
+    return None
 
 
 def poisson_trace(n: int = 2000, rate: float = 200.0, seed: int = 1,
@@ -169,7 +193,7 @@ class Server:
         self.arena_j = Arena(per_buffer)
         # host staging: uploads (chain table, per-admission arrays) and read-backs
         self._h2d = PinnedRing(64, max(n_slots * CHAIN_DTYPE.itemsize, 16 * n_slots + 64))
-        self._d2h = PinnedRing(8, 32 * n_slots + 64)
+        self._d2h = PinnedRing(8, 40 * n_slots + 64)
         self._tile_ring: PinnedRing | None = None
         self.table = np.zeros(n_slots, dtype=CHAIN_DTYPE)
         for s in range(n_slots):
@@ -190,6 +214,9 @@ class Server:
         # slot -> (request, spin offset, coupling offset, admission time, admission iteration)
         self.active: dict[int, tuple[Request, int, int, float, int]] = {}
         self._it = 0  # scheduler iteration of run()
+        self._cancel_lock = threading.Lock()
+        self._cancel_ids: set[int] = set()  # requested by cancel(), taken by run()
+        self._cancelling: set[int] = set()  # resident slots whose budget was zeroed
         self.tiles_dev = None
         self.n_tiles = 0
         self._tiles_dirty = True
@@ -228,6 +255,41 @@ class Server:
         host, k = self._stage(self._h2d, self.table.view(np.uint8))
         self.chains.copy_(host, non_blocking=True)
         self._h2d.guard(k)
+
+    @property
+    def capacity_elements(self) -> int:
+        """Elements of the spin arena (the coupling arena is as large)."""
+        return self.arena_s.size
+
+    def cancel(self, rid: int) -> None:
+        """Cancel request rid (thread-safe; takes effect at the next scheduling step).
+        A request not yet admitted returns at once with status "cancelled" and NaN
+        results; a resident one stops sweeping and returns its energy and magnetisation
+        after the sweeps done so far; one already finished is not affected."""
+        with self._cancel_lock:
+            self._cancel_ids.add(int(rid))
+
+    def _take_cancels(self, pending: deque, queue: deque, t: float) -> list[Result]:
+        with self._cancel_lock:
+            ids, self._cancel_ids = self._cancel_ids, set()
+        if not ids:
+            return []
+        out = []
+        for dq in (pending, queue):
+            keep = [r for r in dq if r.rid not in ids]
+            for r in dq:
+                if r.rid in ids:
+                    out.append(Result(r.rid, math.nan, np.full(3, math.nan), r.arrival, t, t,
+                                      status="cancelled"))
+            dq.clear()
+            dq.extend(keep)
+        slots = [sl for sl, v in self.active.items()
+                 if v[0].rid in ids and sl not in self._cancelling]
+        if slots:
+            idx = self._to_dev(np.asarray(slots, dtype=np.int64))
+            self.remaining.index_fill_(0, idx, 0)  # the next step sweeps them no more
+            self._cancelling.update(slots)
+        return out
 
     def footprint(self, req: Request) -> int:
         return 2 * 3 * req.spins * self.es
@@ -314,16 +376,20 @@ class Server:
                                       _stream(None)))
         idx = self._to_dev(np.asarray(done, dtype=np.int64))
         buf, k = self._d2h.take()
-        both = buf[:32 * n].view(torch.float64).reshape(n, 4)  # m (3) and E per lattice
-        m_E = torch.cat([m_dev[:, 9:12], self.E[idx].unsqueeze(1)], dim=1)
+        # m (3), E and the sweeps made per lattice
+        both = buf[:40 * n].view(torch.float64).reshape(n, 5)
+        m_E = torch.cat([m_dev[:, 9:12], self.E[idx].unsqueeze(1),
+                         self.sweep_ctr[idx].double().unsqueeze(1)], dim=1)
         both.copy_(m_E, non_blocking=True)
         self._d2h.guard(k)
         ev = self._d2h.events[k]
-        m_pin, E_pin = both[:, :3], both[:, 3]
+        m_pin, E_pin = both[:, :3], both[:, 3:]
         info = []
         for s in done:
             req, s_off, j_off, t_adm, it_adm = self.active.pop(s)
-            info.append((req, t_adm, it_adm, self._it))
+            status = "cancelled" if s in self._cancelling else "ok"
+            self._cancelling.discard(s)
+            info.append((req, t_adm, it_adm, self._it, status))
             self.arena_s.release(s_off, 3 * req.spins)
             self.arena_j.release(j_off, 3 * req.spins)
             self._set_dummy(s)
@@ -337,14 +403,19 @@ class Server:
         ev, info, m_pin, E_pin = rec
         ev.synchronize()
         m, E = m_pin.numpy().copy(), E_pin.numpy().copy()
-        return [Result(req.rid, float(E[i]), m[i].copy(), req.arrival, t_adm, t_done, it_adm,
-                       it_fin)
-                for i, (req, t_adm, it_adm, it_fin) in enumerate(info)]
+        return [Result(req.rid, float(E[i, 0]), m[i].copy(), req.arrival, t_adm, t_done, it_adm,
+                       it_fin, status, int(E[i, 1]))
+                for i, (req, t_adm, it_adm, it_fin, status) in enumerate(info)]
 
     # -------------------------------------------------------------------- loop
-    def run(self, trace: list[Request], realtime: bool = True) -> list[Result]:
+    def run(self, trace: list[Request], realtime: bool = True,
+            on_iteration=None) -> list[Result]:
         """Serve a trace.  realtime=True releases each request at its arrival time
-        (wall clock from the start of the run); False releases all at once.
+        (wall clock from the start of the run); False releases all at once.  A request
+        that cannot be served (request_problem) returns at its arrival with status
+        "rejected: ..." and does not affect the others; cancel() may be called from
+        another thread, or from on_iteration(iteration, server), called after every
+        scheduling step.
 
         Each iteration: admit what fits, enqueue one step for the resident lattices and
         a non-blocking copy of their remaining budgets, then wait for the PREVIOUS
@@ -369,8 +440,15 @@ class Server:
         while pending or queue or self.active or prev is not None or retiring:
             c0 = clock()
             t = now()
+            results.extend(self._take_cancels(pending, queue, t))
             while pending and (not realtime or pending[0].arrival <= t):
-                queue.append(pending.popleft())
+                req = pending.popleft()
+                why = request_problem(req, self.capacity_elements)
+                if why is None:
+                    queue.append(req)
+                else:
+                    results.append(Result(req.rid, math.nan, np.full(3, math.nan), req.arrival,
+                                          t, t, status=f"rejected: {why}"))
             admitted = []
             while queue and self.try_admit(queue[0], now()):
                 admitted.append(self._slot_of(queue.popleft()))
@@ -418,6 +496,8 @@ class Server:
             prev = cur
             it += 1
             self._it = it
+            if on_iteration is not None:
+                on_iteration(it, self)
             if prev is None and not retiring and not self.active:
                 if queue:
                     raise RuntimeError(f"request {queue[0].rid} does not fit the HBM budget")
@@ -435,7 +515,13 @@ class Server:
 
 
 def latency_stats(results: list[Result]) -> dict:
-    lat = np.array([r.latency for r in results])
-    return {"n": int(lat.size), "p50_s": float(np.percentile(lat, 50)),
-            "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
-            "max_s": float(lat.max())}
+    """Latency percentiles of the completed requests (status "ok"); cancelled and
+    rejected ones are counted apart."""
+    lat = np.array([r.latency for r in results if r.status == "ok"])
+    out = {"n": int(lat.size), "cancelled": sum(r.status == "cancelled" for r in results),
+           "rejected": sum(r.status.startswith("rejected") for r in results)}
+    if lat.size:
+        out.update({"p50_s": float(np.percentile(lat, 50)),
+                    "p99_s": float(np.percentile(lat, 99)), "mean_s": float(lat.mean()),
+                    "max_s": float(lat.max())})
+    return out

@@ -4,6 +4,8 @@ instead of failing, and the multi-lattice pass sweep equals the chain-per-workgr
 sweep."""
 from __future__ import annotations
 
+import math
+
 import numpy as np
 import pytest
 
@@ -104,11 +106,67 @@ def test_admission_waits_for_memory(mods):
     assert srv.free_slots and len(srv.free_slots) == 8
 
 
-def test_request_larger_than_budget_is_rejected(mods):
+def alone(S, req):
+    return S.Server(hbm_budget=64 << 20, n_slots=4, step_sweeps=5).run([req], realtime=False)[0]
+
+
+def test_unservable_requests_are_rejected_without_affecting_others(mods):
+    """Requests that cannot be served (odd or too large L, no hit, T <= 0, a footprint
+    over the budget) return at once with a reason; the others complete as if alone."""
     hsg, B, S = mods
-    srv = S.Server(hbm_budget=1 << 20, n_slots=2)
-    with pytest.raises(RuntimeError):
-        srv.run([S.Request(rid=0, seed=1, L=64, T=0.5, sweeps=5, k=1)], realtime=False)
+    good = [S.Request(rid=r, seed=7000 + r, L=L, T=0.6, sweeps=20, k=k)
+            for r, (L, k) in enumerate([(8, 1), (16, 4), (32, 1)])]
+    bad = [S.Request(rid=10, seed=1, L=9, T=0.5, sweeps=5, k=1),
+           S.Request(rid=11, seed=1, L=B.BATCH_L_MAX + 2, T=0.5, sweeps=5, k=1),
+           S.Request(rid=12, seed=1, L=8, T=0.5, sweeps=5, k=0),
+           S.Request(rid=13, seed=1, L=8, T=0.0, sweeps=5, k=1),
+           S.Request(rid=14, seed=1, L=96, T=0.5, sweeps=5, k=1)]  # beyond a 4 MB budget
+    trace = [bad[0], good[0], bad[1], bad[2], good[1], bad[3], bad[4], good[2]]
+    res = {r.rid: r for r in S.Server(hbm_budget=4 << 20, n_slots=8, step_sweeps=6).run(
+        trace, realtime=False)}
+    assert sorted(res) == sorted(r.rid for r in trace)
+    for r in bad:
+        print(f"[serve] rid={r.rid}: {res[r.rid].status}")
+        assert res[r.rid].status.startswith("rejected: ") and math.isnan(res[r.rid].E)
+        assert res[r.rid].sweeps_done == -1
+    for r in good:
+        a, b = alone(S, r), res[r.rid]
+        assert b.status == "ok" and b.sweeps_done == r.sweeps
+        np.testing.assert_array_equal(a.m, b.m)
+        assert abs(a.E - b.E) <= 1e-12 * max(1.0, abs(a.E))
+
+
+def test_cancel_resident_and_queued_requests(mods):
+    """cancel() from the iteration hook: a resident long request stops and returns the
+    state after the sweeps it made (equal to an alone run of that many sweeps); a queued
+    one returns at once, never admitted; the others are unaffected."""
+    hsg, B, S = mods
+    long = S.Request(rid=0, seed=8100, L=32, T=0.4, sweeps=100000, k=4)
+    short = [S.Request(rid=r, seed=8100 + r, L=16, T=0.7, sweeps=30, k=1) for r in (1, 2)]
+    queued = S.Request(rid=3, seed=8200, L=16, T=0.7, sweeps=30, k=1)
+    srv = S.Server(hbm_budget=64 << 20, n_slots=3, step_sweeps=4)  # queued waits for a slot
+
+    def hook(it, server):
+        if it == 2:
+            server.cancel(0)
+            server.cancel(3)
+            server.cancel(12345)  # unknown: ignored
+
+    res = {r.rid: r for r in srv.run([long, *short, queued], realtime=False, on_iteration=hook)}
+    assert sorted(res) == [0, 1, 2, 3]
+    c = res[0]
+    print(f"[serve] cancelled after {c.sweeps_done} sweeps, E={c.E:.6f}")
+    assert c.status == "cancelled" and 0 < c.sweeps_done < long.sweeps
+    a = alone(S, S.Request(rid=0, seed=long.seed, L=long.L, T=long.T, sweeps=c.sweeps_done,
+                           k=long.k))
+    np.testing.assert_array_equal(a.m, c.m)
+    assert abs(a.E - c.E) <= 1e-12 * max(1.0, abs(a.E))
+    q = res[3]
+    assert q.status == "cancelled" and q.sweeps_done == -1 and math.isnan(q.E)
+    for r in short:
+        assert res[r.rid].status == "ok" and res[r.rid].sweeps_done == r.sweeps
+        np.testing.assert_array_equal(alone(S, r).m, res[r.rid].m)
+    assert len(srv.free_slots) == 3 and not srv.active
 
 
 def test_pass_sweep_equals_chain_sweep(mods):

@@ -1,7 +1,8 @@
-"""Host logic of the served form (no GPU): the request stream, the arena allocator
-and the latency statistics."""
+"""Host logic of the served form (no GPU): the request stream, the arena allocator,
+request validation and the latency statistics."""
 from __future__ import annotations
 
+import dataclasses
 import math
 
 import numpy as np
@@ -52,6 +53,34 @@ def test_latency_stats():
     st = S.latency_stats(res)
     assert st["n"] == 100 and st["p50_s"] == pytest.approx(50.5) and st["max_s"] == 100
     assert st["p99_s"] == pytest.approx(99.01)
+
+
+def test_latency_stats_count_completed_requests_only():
+    res = [S.Result(i, 0.0, np.zeros(3), arrival=0.0, admitted=0.0, finished=float(i))
+           for i in range(1, 11)]
+    res.append(S.Result(99, float("nan"), np.full(3, np.nan), 5.0, 0.0, 0.0, status="cancelled"))
+    res.append(S.Result(98, float("nan"), np.full(3, np.nan), 5.0, 0.0, 0.0,
+                        status="rejected: L=3 must be even"))
+    st = S.latency_stats(res)
+    assert st["n"] == 10 and st["cancelled"] == 1 and st["rejected"] == 1
+    assert st["max_s"] == 10
+
+
+def test_request_problem():
+    ok = S.Request(rid=0, seed=1, L=16, T=0.5, sweeps=10, k=4)
+    cap = 3 * 16 ** 3
+    assert S.request_problem(ok, cap) is None
+    assert S.request_problem(dataclasses.replace(ok, T=float("inf")), cap) is None  # beta = 0
+    assert S.request_problem(dataclasses.replace(ok, sweeps=0), cap) is None
+    bad = {"L": [3, 0, S.BATCH_L_MAX + 2], "k": [0, 70000], "T": [0.0, -1.0, float("nan")],
+           "sweeps": [-1], "seed": [-1, 2 ** 64]}
+    for field, values in bad.items():
+        for v in values:
+            assert S.request_problem(dataclasses.replace(ok, **{field: v}), 10 ** 9), (field, v)
+    # the footprint against the arena, in its 64-element blocks
+    assert S.request_problem(ok, cap - 1) is not None
+    small = dataclasses.replace(ok, L=2)  # 24 elements take one block of 64
+    assert S.request_problem(small, 64) is None and S.request_problem(small, 63) is not None
 
 
 def test_autotune_pick_caches_the_fastest(tmp_path):
