@@ -605,9 +605,10 @@ int hsg_batch_check(const hsg_chain* c, int32_t n, int64_t spin_elems, int64_t J
     if (ch.flags & ~(HSG_HEAT_BATH | HSG_CHAIN_INIT_J) || ch.reserved != 0)
       return fail(HSG_EINVAL, "chain %d: unknown flags 0x%x", (int)i, (unsigned)ch.flags);
     const int64_t n_el = (int64_t)3 * ch.L * ch.L * ch.L;
-    if (ch.spin_offset < 0 || ch.spin_offset + n_el > spin_elems)
+    // offset <= elems - n_el: no sum that could pass the int64 range
+    if (ch.spin_offset < 0 || spin_elems < n_el || ch.spin_offset > spin_elems - n_el)
       return fail(HSG_EINVAL, "chain %d: spins outside the spin buffer", (int)i);
-    if (ch.J_offset < 0 || ch.J_offset + n_el > J_elems)
+    if (ch.J_offset < 0 || J_elems < n_el || ch.J_offset > J_elems - n_el)
       return fail(HSG_EINVAL, "chain %d: couplings outside the coupling buffer", (int)i);
     ranges.emplace_back(ch.spin_offset, ch.spin_offset + n_el);
   }
