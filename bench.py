@@ -695,21 +695,31 @@ def fit_multi_hit(ms_by_k: dict, ms0: float, N: int) -> dict:
 
 def large_lattice_leg(hsg, torch, args) -> dict:
     """The largest lattice of the large-lattice configuration, L = 512 (134M spins),
-    binary32, the headline sweep (k + n_or, T, renormalisation), the library's traversal."""
+    binary32 and binary64 (3.2 and 6.4 GB of spins and couplings), the headline sweep
+    (k + n_or, T, renormalisation), the library's traversal for each precision."""
     L = 512
-    lat = hsg.Lattice(L, torch.float32, seed=1)
-    flags = hsg.default_flags(L, torch.float32)
-    steps = max(4, args.steps // 5)
-    ms = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=args.renorm_every,
-                     steps=steps, warmup=2, flags=flags)
     N = L ** 3
-    del lat
-    torch.cuda.empty_cache()
-    return {"L": L, "dtype": "f32", "k": args.k, "n_or": args.n_or, "steps": steps,
-            "flags": flags, "ms_per_step": ms,
-            "spin_updates_per_ns": N * (args.k + args.n_or) / (ms * 1e6),
-            "hbm_frac_36B": N * (1 + args.n_or) * BYTES_PER_SITE_PHASE / (ms * 1e-3) / 1e9 /
-            HBM_PEAK_GBS}
+    out = {}
+    for dt, name, scale in ((torch.float32, "f32", 1), (torch.float64, "f64", 2)):
+        lat = hsg.Lattice(L, dt, seed=1)
+        flags = hsg.default_flags(L, dt)
+        steps = max(4, args.steps // 5) if scale == 1 else 4
+        ms = time_sweeps(lat, torch, T=args.T, k=args.k, n_or=args.n_or, R=args.renorm_every,
+                         steps=steps, warmup=2, flags=flags)
+        del lat
+        torch.cuda.empty_cache()
+        rec = {"L": L, "dtype": name, "k": args.k, "n_or": args.n_or, "steps": steps,
+               "flags": flags, "ms_per_step": ms,
+               "spin_updates_per_ns": N * (args.k + args.n_or) / (ms * 1e6)}
+        # the same byte model in each precision: 36 B per site and phase in binary32, 72 B
+        # in binary64
+        rec[f"hbm_frac_{int(36 * scale)}B"] = (N * (1 + args.n_or) * BYTES_PER_SITE_PHASE * scale
+                                              / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        if scale == 1:
+            out.update(rec)
+        else:
+            out["binary64"] = rec
+    return out
 
 
 def main():
