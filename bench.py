@@ -783,6 +783,10 @@ def main():
                    key=lambda kd: launches[kd]["total_ms"])
     roofline = kernel_roofline(dom_kind, launches[dom_kind], N, counted=L == 256 and args.k == 4)
     roofline["launches"] = {hsg.LAUNCH_NAMES[kd]: v for kd, v in launches.items()}
+    # the event-timed call's launches summed per sweep, against ms_per_step of the plain
+    # call (the timed region): the per-launch durations account for the whole sweep
+    roofline["launches_sum_ms_per_step"] = (sum(v["total_ms"] for v in launches.values())
+                                            / args.steps)
     note(f"roofline: {roofline['kernel']} {roofline['kernel_ms'] * 1e3:.1f} us, "
          f"frac {roofline['frac']:.3f}")
     copy = copy_bandwidth(torch)
