@@ -1,7 +1,7 @@
 """GPU tests of the served form: results do not depend on what else is resident
-(alone vs in the mix), match the single-lattice path, admission by footprint waits
-instead of failing, and the multi-lattice pass sweep equals the chain-per-workgroup
-sweep."""
+(alone vs in the mix), match the single-lattice path (also on the served stream's own mix
+of sizes and arrivals), admission by footprint waits instead of failing, and the
+multi-lattice pass sweep equals the chain-per-workgroup sweep."""
 from __future__ import annotations
 
 import math
@@ -63,6 +63,30 @@ def test_results_match_single_lattice_path(mods):
         E = lat.energy().item()
         np.testing.assert_allclose(res[req.rid].m, m, rtol=0, atol=1e-12)
         assert abs(res[req.rid].E - E) <= 1e-10 * max(1.0, abs(E))
+
+
+def test_served_stream_matches_single_lattice_path(mods):
+    """The served stream's own mix (L in {8, ..., 96}, k in {1, 4}, Poisson arrivals at
+    200 per second, served in real time so requests join while others run), with the
+    sweep counts capped at 300: every result equals the single-lattice path's."""
+    hsg, B, S = mods
+    trace = S.poisson_trace(n=60, rate=200.0, seed=1)
+    for r in trace:
+        r.sweeps = min(r.sweeps, 300)
+    assert {r.L for r in trace} == {8, 16, 32, 64, 96}
+    srv = S.Server(hbm_budget=1 << 30, n_slots=64, step_sweeps=16, tile_sites=512)
+    res = {r.rid: r for r in srv.run(trace, realtime=True)}
+    assert sorted(res) == [r.rid for r in trace]
+    assert all(r.status == "ok" and r.sweeps_done == q.sweeps for q in trace
+               for r in [res[q.rid]])
+    for req in trace:
+        lat = hsg.Lattice(req.L, torch.float32, seed=req.seed)
+        lat.sweep(T=req.T, k=req.k, n_sweeps=req.sweeps)
+        m = lat.export()[0].double().mean(dim=1).cpu().numpy()
+        E = lat.energy().item()
+        np.testing.assert_allclose(res[req.rid].m, m, rtol=0, atol=1e-12, err_msg=str(req))
+        assert abs(res[req.rid].E - E) <= 1e-10 * max(1.0, abs(E)), req
+    print(f"[serve] {len(trace)} requests, {srv.stats['steps']} steps")
 
 
 @pytest.mark.parametrize("L,k,T", [(8, 4, 0.6), (16, 1, 0.3)])
