@@ -728,7 +728,7 @@ def main():
         reduce_counters(*args.reduce_counters)
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU: this build has no multi-GPU path (asked for "
+        print(f"bench.py runs on one GPU: the library has no multi-GPU path (asked for "
               f"--gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
     import torch

@@ -47,7 +47,7 @@ extern "C" {
 #define HSG_OK 0
 #define HSG_EINVAL (-1)      /* an argument is out of range or a required pointer is NULL */
 #define HSG_EDEVICE (-3)     /* a HIP call or kernel launch failed */
-#define HSG_EUNSUPPORTED (-4) /* valid request that this build does not implement */
+#define HSG_EUNSUPPORTED (-4) /* valid request that the library does not implement */
 
 #define HSG_F32 0 /* binary32 spins and couplings */
 #define HSG_F64 1 /* binary64 spins and couplings */
